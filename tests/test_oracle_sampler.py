@@ -1,0 +1,210 @@
+"""Pins of the oracle's Gibbs sweep (oracle.sampler) against mathematics that
+does not go through the messenger field.
+
+* noise-free iteration  -> dense closed-form Wiener mean (exact fixed point)
+* fixed-P chain         -> dense Wiener posterior mean and variance (MC error)
+* uniform noise, no mask -> one sweep is the textbook per-mode Wiener posterior
+* P(k) step             -> scipy.stats.invgamma (KS)
+* every sweep           -> Parseval, exact Hermitian symmetry
+* joint (s, P) chain    -> an exact-block sampler (s | P by dense Cholesky)
+"""
+import numpy as np
+import pytest
+import scipy.stats
+
+from oracle import sampler, shells, wiener
+from paper_1402_1763_amd import workloads
+
+
+def _problem(n, n_bins, mask="random", seed=7, **kw):
+    w = workloads.small_workload(n, n_bins, mask=mask, precision="fp64", seed=seed, **kw)
+    pb = workloads.make_problem(w)
+    prob = sampler.make_problem(pb["data"], pb["noise_var"], n_bins, w.box, seed=1234 + seed)
+    return w, pb, prob
+
+
+def _batch_z(samples, target, n_batches):
+    """z-scores of the chain mean against target, errors from batch means."""
+    nb = len(samples) // n_batches
+    means = samples[: nb * n_batches].reshape(n_batches, nb, -1).mean(axis=1)
+    se = means.std(axis=0, ddof=1) / np.sqrt(n_batches)
+    return (means.mean(axis=0) - target) / se
+
+
+def test_noise_free_iteration_reaches_wiener_mean():
+    w, pb, prob = _problem(8, 4)
+    p_grid = np.array([40.0, 12.0, 5.0, 2.0]) * prob.tau
+    mean, _ = wiener.posterior(8, 4, p_grid, pb["data"], pb["noise_var"])
+    st = sampler.State(s=np.zeros((8, 8, 8)), p_grid=p_grid)
+    st = sampler.run_chain(prob, st, 2000, noise=False)
+    err = np.abs(st.s.ravel() - mean).max() / np.sqrt(np.mean(mean ** 2))
+    assert err < 1e-10
+
+
+def test_noise_free_iteration_survey_mask_16():
+    w, pb, prob = _problem(16, 6, mask="survey", box=16 * 62.5, nbar=3e-4, sel_r0=400.0)
+    p_grid = np.linspace(8.0, 1.0, 6) * prob.tau
+    mean, _ = wiener.posterior(16, 6, p_grid, pb["data"], pb["noise_var"])
+    st = sampler.State(s=np.zeros((16,) * 3), p_grid=p_grid)
+    st = sampler.run_chain(prob, st, 1500, noise=False)
+    err = np.abs(st.s.ravel() - mean).max() / np.sqrt(np.mean(mean ** 2))
+    assert err < 1e-10
+
+
+def test_messenger_step_limits():
+    w, pb, prob = _problem(8, 4)
+    s = np.random.default_rng(0).standard_normal((8, 8, 8))
+    mu, var = sampler.messenger_moments(s, prob)
+    obs = prob.observed
+    i = np.unravel_index(np.argmin(np.where(obs, prob.noise_var, np.inf)), s.shape)
+    assert var[i] == 0.0 and mu[i] == pb["data"][i]       # N~ = 0: t = d exactly
+    assert np.all(mu[~obs] == s[~obs]) and np.all(var[~obs] == prob.tau)
+    # on observed voxels the messenger interpolates d and s with weight tau / N
+    wgt = prob.tau / prob.noise_var[obs]
+    assert np.allclose(mu[obs], wgt * pb["data"][obs] + (1 - wgt) * s[obs], rtol=0, atol=1e-12)
+    assert np.allclose(var[obs], prob.tau * (1 - wgt), rtol=1e-12, atol=0)
+
+
+def test_uniform_noise_one_sweep_is_textbook_wiener():
+    n, nbins = 8, 4
+    w, pb, prob = _problem(n, nbins, mask="none")
+    m = n ** 3
+    sig2 = prob.tau
+    assert np.all(prob.noise_var == sig2)
+    p_grid = np.array([30.0, 10.0, 3.0, 1.0])
+    diag = {}
+    st = sampler.sweep(prob, sampler.State(s=np.zeros((n,) * 3), p_grid=p_grid),
+                       sample_pk=False, diagnostics=diag)
+    assert np.array_equal(diag["t"], pb["data"])          # messenger variance is zero
+    # per-mode Wiener posterior with white noise of power sig2 per voxel
+    d_hat = np.fft.rfftn(pb["data"])
+    b = shells.bin_of_q(shells.half_grid_q(n), n, nbins)
+    p = np.where(b >= 0, p_grid[np.maximum(b, 0)], 0.0)
+    post_mean = p / (p + sig2) * d_hat
+    post_var = m * p * sig2 / (p + sig2)      # zero only at k = 0
+    resid = diag["s_hat"] - post_mean
+    # the random part has the posterior variance, split over re and im halves
+    # (self-conjugate modes are real and are left out here)
+    sc = np.zeros_like(p, dtype=bool)
+    for i in (0, n // 2):
+        for j in (0, n // 2):
+            for k in (0, n // 2):
+                sc[i, j, k] = True
+    sel = (p > 0) & ~sc
+    sd = np.sqrt(post_var[sel] / 2)
+    z = np.concatenate([resid.real[sel] / sd, resid.imag[sel] / sd])
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-4
+    # and it is exactly the contract's draw: check the k = (1, 0, 0) mode
+    g_re, g_im = sampler.signal_normals(n, prob.seed, prob.chain, 0)
+    k = (1, 0, 0)
+    expect = post_mean[k] + np.sqrt(post_var[k] / 2) * (g_re[k] + 1j * g_im[k])
+    assert abs(diag["s_hat"][k] - expect) < 1e-12 * abs(expect)
+
+
+def test_power_draw_is_inverse_gamma():
+    n, nbins = 16, 5
+    w, pb, prob = _problem(n, nbins)
+    rng = np.random.default_rng(3)
+    s_hat = np.fft.rfftn(rng.standard_normal((n,) * 3) * 2.0)
+    sigma = sampler.shell_power(s_hat, prob)
+    counts = shells.mode_counts(n, nbins)
+    draws = []
+    for sweep in range(400):
+        draws.append(sampler.power_step(sigma, np.ones(nbins), prob, sweep))
+    draws = np.array(draws)
+    for b in range(nbins):
+        dist = scipy.stats.invgamma(counts[b] / 2.0, scale=sigma[b] / (2.0 * prob.m))
+        assert scipy.stats.kstest(draws[:, b], dist.cdf).pvalue > 1e-3
+
+
+def test_shell_power_is_full_grid_sum_and_parseval():
+    n, nbins = 8, 4
+    w, pb, prob = _problem(n, nbins)
+    st = sampler.State(s=np.zeros((n,) * 3), p_grid=pb["pk_init"] / w.cell_volume)
+    for _ in range(5):
+        diag = {}
+        st = sampler.sweep(prob, st, diagnostics=diag)
+        s_hat = diag["s_hat"]
+        # Hermitian exactly on the iz in {0, N/2} planes
+        for iz in (0, n // 2):
+            plane = s_hat[:, :, iz]
+            j = (-np.arange(n)) % n
+            assert np.array_equal(plane, np.conj(plane[j][:, j]))
+        # shell power = full-grid sum by bins, computed from the full DFT of s
+        full = np.fft.fftn(st.s)
+        m = shells.integer_wavenumbers(n)
+        q = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
+        bf = shells.bin_of_q(q, n, nbins)
+        ref = np.bincount(bf[bf >= 0], weights=np.abs(full[bf >= 0]) ** 2, minlength=nbins)
+        assert np.allclose(diag["sigma"], ref, rtol=1e-10)
+        # Parseval: sum_x s^2 = (1/M) sum_b sigma_b (the k = 0 mode is zero)
+        assert np.isclose((st.s ** 2).sum(), diag["sigma"].sum() / n ** 3, rtol=1e-10)
+        assert abs(full[0, 0, 0]) < 1e-9
+
+
+@pytest.mark.slow
+def test_fixed_power_chain_matches_dense_posterior():
+    n, nbins = 8, 4
+    w, pb, prob = _problem(n, nbins, seed=21)
+    p_grid = np.array([4.0, 3.0, 2.0, 1.0]) * prob.tau
+    mean, cov = wiener.posterior(n, nbins, p_grid, pb["data"], pb["noise_var"])
+    st = sampler.State(s=mean.reshape((n,) * 3).copy(), p_grid=p_grid)
+    samples = []
+    for _ in range(6000):
+        st = sampler.sweep(prob, st, sample_pk=False)
+        samples.append(st.s.ravel())
+    samples = np.array(samples)
+    z = _batch_z(samples, mean, 60)
+    assert 0.75 < np.mean(z ** 2) < 1.35
+    assert np.max(np.abs(z)) < 4.8
+    zv = _batch_z((samples - mean) ** 2, np.diag(cov), 60)
+    assert 0.6 < np.mean(zv ** 2) < 1.6
+    assert np.max(np.abs(zv)) < 5.0
+
+
+@pytest.mark.slow
+def test_joint_chain_matches_exact_block_sampler():
+    """Messenger Gibbs over (s, P) against an exact-block Gibbs sampler whose
+    s | P step is a dense Cholesky draw and whose P | s step is scipy's
+    inverse-gamma on full-grid shell sums."""
+    n, nbins = 4, 2
+    w, pb, prob = _problem(n, nbins, mask="none", seed=5, noise_lo=0.5, noise_hi=2.0,
+                           amp=2e4, index=0.0)
+    m = n ** 3
+    counts = shells.mode_counts(n, nbins)
+    p0 = np.array([20.0, 10.0])
+    n_steps = 12000
+    # messenger chain
+    st = sampler.State(s=np.zeros((n,) * 3), p_grid=p0.copy())
+    ch_m = []
+    for _ in range(n_steps):
+        st = sampler.sweep(prob, st)
+        ch_m.append(np.concatenate([np.log(st.p_grid), st.s.ravel()[:8]]))
+    # exact-block chain
+    rng = np.random.default_rng(17)
+    kk = shells.integer_wavenumbers(n)
+    q = kk[:, None, None] ** 2 + kk[None, :, None] ** 2 + kk[None, None, :] ** 2
+    bf = shells.bin_of_q(q, n, nbins)
+    p = p0.copy()
+    ch_d = []
+    for _ in range(n_steps):
+        mean, cov = wiener.posterior(n, nbins, p, pb["data"], pb["noise_var"])
+        s = wiener.draw(mean, cov, rng).reshape((n,) * 3)
+        full = np.abs(np.fft.fftn(s)) ** 2
+        sig = np.bincount(bf[bf >= 0], weights=full[bf >= 0], minlength=nbins)
+        p = np.array([scipy.stats.invgamma(counts[b] / 2.0, scale=sig[b] / (2.0 * m)).rvs(
+            random_state=rng) for b in range(nbins)])
+        ch_d.append(np.concatenate([np.log(p), s.ravel()[:8]]))
+    ch_m = np.array(ch_m[500:])
+    ch_d = np.array(ch_d[500:])
+    nbat = 50
+
+    def batch(ch):
+        k = len(ch) // nbat
+        mb = ch[: k * nbat].reshape(nbat, k, -1).mean(axis=1)
+        return mb.mean(axis=0), mb.std(axis=0, ddof=1) / np.sqrt(nbat)
+
+    mm, sm = batch(ch_m)
+    md, sd = batch(ch_d)
+    z = (mm - md) / np.sqrt(sm ** 2 + sd ** 2)
+    assert np.max(np.abs(z)) < 4.5, z
