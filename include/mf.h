@@ -1,0 +1,163 @@
+/*
+ * mf.h -- C ABI of the MI355X messenger-field Gibbs sampler.
+ *
+ * The library samples the joint posterior of a signal s on a periodic N^3 grid
+ * and its isotropic power spectrum P(k), given data d = R s + noise with a
+ * diagonal noise covariance N (Jasche & Lavaux 2014, "Matrix-free large scale
+ * Bayesian inference in cosmology", Sec. 2 model, Sec. 3 sampler).  One Gibbs
+ * sweep (Algs. 1 and 2 of that paper, P(k) averaged over |k| shells):
+ *   1. messenger t ~ Pi(t | T, d, s), voxel by voxel (eqs. for mu^t, sigma^t),
+ *   2. forward 3D FFT of t,
+ *   3. signal s^ ~ Pi(s^ | S, T, t^), mode by mode (eqs. for mu^s, sigma^s),
+ *   4. shell sums of |s^|^2 and P_b ~ InvGamma(n_b/2, sigma_b/(2M)) under
+ *      Jeffreys' prior (eq. of the inverse-gamma conditional, Alg. 2),
+ *   5. inverse 3D FFT of s^.
+ * T = tau * 1 with tau = the smallest observed noise variance (Sec. 2, the
+ * positivity bound on the augmented noise N - R^T T R).
+ *
+ * Conventions
+ *  - Grids are C order (ix, iy, iz), iz fastest, M = N^3 voxels.
+ *  - Unobserved voxels are marked by noise_var = +INF (R_i = 0); their data
+ *    value is ignored.
+ *  - Power is given and returned per bin in physical units (volume, h^-3
+ *    Mpc^3 when the box side is in h^-1 Mpc); bin b holds the modes with
+ *    b*dk <= |k| < (b+1)*dk, dk = sqrt(3) * pi * N / (box * n_bins), edges
+ *    compared in exact integer arithmetic, the corner mode in the last bin,
+ *    k = 0 in no bin.
+ *  - Random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
+ *    (element, sweep, phase, chain id).  A chain is a pure function of
+ *    (inputs, seed, chain id, sweep index): there is no generator state.
+ *  - Memory: the caller owns every host array (copied during the call) and the
+ *    device workspace (size from mf_workspace_bytes, at least 256-byte
+ *    aligned), which must outlive the problem handle; the library allocates
+ *    no device memory.  The handle owns small host metadata only.
+ *  - Streams: `stream` is a hipStream_t (NULL = default stream).  Sweeps are
+ *    enqueued asynchronously; functions that return host data synchronise the
+ *    stream.
+ *  - Errors: every call returns an mf_status; mf_last_error() gives a
+ *    thread-local message for the last non-OK status.  No call throws.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MF_OK = 0,
+  MF_E_INVALID_ARG = -1,      /* null pointer, bad count, bad descriptor field */
+  MF_E_UNSUPPORTED_SIZE = -2, /* N is not a supported FFT size */
+  MF_E_TAU = -3,              /* tau above the smallest observed noise variance */
+  MF_E_NONFINITE = -4,        /* NaN input, or a non-finite P / shell sum on device */
+  MF_E_DEVICE = -5,           /* a HIP call or kernel launch failed */
+  MF_E_WORKSPACE = -6,        /* workspace missing, misaligned or too small */
+  MF_E_STATE = -7             /* chain index out of range, or handle misuse */
+} mf_status;
+
+typedef enum {
+  MF_PREC_FP64 = 0, /* every step in FP64 */
+  MF_PREC_FP32 = 1  /* fields, FFTs and pointwise draws in FP32; shell sums,
+                       inverse-gamma draws and per-bin tables in FP64 */
+} mf_precision;
+
+typedef struct {
+  int32_t n;          /* grid side N: a power of two, 8 <= N <= 512 */
+  int32_t n_bins;     /* number of |k| bins, 1 <= n_bins <= 1024 */
+  double box;         /* box side L (> 0) */
+  double tau;         /* messenger variance; <= 0 selects min observed N_i */
+  uint64_t seed;      /* Philox key */
+  uint32_t chain_id;  /* counter word 3 of chain 0; chain c uses chain_id + c */
+  int32_t precision;  /* mf_precision */
+  int32_t sample_pk;  /* 1: Gibbs update of P(k) each sweep; 0: P held fixed */
+  int32_t n_chains;   /* independent chains sharing N, bins, box and seed (>= 1) */
+} mf_chain_desc;
+
+typedef struct mf_problem mf_problem;
+
+/* Number of sweep kernels reported by mf_gibbs_sweep_timed, in launch order:
+ * 0 z-pass (inverse z-FFT, messenger draw, forward z-FFT), 1 forward y-FFT,
+ * 2 x-pass (forward x-FFT, signal draw, shell sums, inverse x-FFT),
+ * 3 P(k) draw, 4 inverse y-FFT. */
+#define MF_NUM_KERNELS 5
+
+/* Returns 1 if N is a supported grid side, else 0. */
+int32_t mf_supported_n(int32_t n);
+
+/* Device workspace bytes needed by a problem with this descriptor.
+ * Errors: MF_E_INVALID_ARG, MF_E_UNSUPPORTED_SIZE. */
+mf_status mf_workspace_bytes(const mf_chain_desc* desc, size_t* bytes);
+
+/* Set up a problem (model of Sec. 2: data model, messenger covariance tau).
+ *  data[c], noise_var[c]: host, M doubles each, chain c's data and noise
+ *      variance (+INF = unobserved).  Observed voxels need finite d and N > 0.
+ *  pk_init[c]: host, n_bins doubles, initial P per bin (physical units, >= 0).
+ *  s_init: NULL (every chain starts at s = 0) or host array of n_chains
+ *      pointers, each M doubles (a NULL entry also means s = 0).
+ *  workspace: device pointer of workspace_bytes >= mf_workspace_bytes(desc).
+ * Per chain, tau is the smallest observed N_i unless desc->tau > 0, which
+ * must not exceed it (MF_E_TAU).  Per-voxel coefficients are formed in FP64
+ * on the host and uploaded.  Enqueues on `stream` and synchronises it.
+ * Errors: MF_E_INVALID_ARG, MF_E_UNSUPPORTED_SIZE, MF_E_TAU, MF_E_NONFINITE,
+ * MF_E_WORKSPACE, MF_E_DEVICE.  On error *out is NULL. */
+mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
+                          const double* const* noise_var, const double* const* pk_init,
+                          const double* const* s_init, void* workspace, size_t workspace_bytes,
+                          void* stream, mf_problem** out);
+
+/* Enqueue n_sweeps >= 0 Gibbs sweeps of every chain (Algs. 1 and 2 with shell
+ * averaging; the P(k) step only when sample_pk = 1).  Asynchronous.
+ * Errors: MF_E_INVALID_ARG, MF_E_DEVICE. */
+mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
+
+/* As mf_gibbs_sweep, but records HIP events around every kernel, synchronises,
+ * and writes the mean duration in milliseconds of each of the first
+ * min(n_kernels, MF_NUM_KERNELS) sweep kernels to kernel_ms (host). */
+mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream,
+                               double* kernel_ms, int32_t n_kernels);
+
+/* Copy chain `chain`'s state to the host: s_out (M doubles, may be NULL),
+ * pk_out (n_bins doubles, physical units, may be NULL), sweep_out (number of
+ * sweeps done, may be NULL).  Synchronises `stream`.
+ * Errors: MF_E_STATE (bad chain), MF_E_NONFINITE (the device flagged a
+ * non-finite shell sum or P draw), MF_E_DEVICE. */
+mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double* pk_out,
+                             uint64_t* sweep_out, void* stream);
+
+/* Overwrite chain `chain`'s s (M doubles, NULL keeps s) and P (n_bins
+ * doubles, NULL keeps P) and set the sweep counter of the whole problem to
+ * `sweep` (the counter is shared by all chains).  Continuing from a state
+ * read by mf_get_chain_state reproduces the original chain.
+ * Errors: MF_E_STATE, MF_E_INVALID_ARG, MF_E_NONFINITE, MF_E_DEVICE. */
+mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, const double* pk,
+                             uint64_t sweep, void* stream);
+
+/* The messenger variance tau of a chain (host value). */
+mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out);
+
+/* Diagnostics (used by the tests to check single passes).
+ * mf_debug_run_kernel: enqueue one sweep kernel (numbering as in
+ * MF_NUM_KERNELS) for every chain with sweep index `sweep`.
+ * mf_debug_spectrum: copy chain `chain`'s half-complex working buffer to
+ * (to_device = 0) or from (to_device = 1) the host array `buf` of
+ * 2 * (N/2 + 1) * N * N doubles, laid out [kz][ix][iy][re, im] with
+ * kz in [0, N/2] -- the buffer holds the field transformed along whichever
+ * axes the passes run so far have transformed.  Synchronises `stream`. */
+mf_status mf_debug_run_kernel(mf_problem* p, int32_t kernel, uint64_t sweep, void* stream);
+mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t to_device,
+                            void* stream);
+
+/* Release the handle (not the workspace).  NULL is ignored. */
+void mf_destroy_problem(mf_problem* p);
+
+/* Thread-local message describing the last non-OK status (never NULL). */
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

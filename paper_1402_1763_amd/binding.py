@@ -1,0 +1,284 @@
+"""ctypes binding of libmfgibbs.so (the C ABI in include/mf.h).
+
+Argument marshalling only: every step of a sweep runs in the library's HIP
+kernels.  PyTorch provides the device workspace and the stream.  The module
+raises ImportError-like errors when the library has not been built; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfgibbs.so")
+
+MF_OK = 0
+MF_E_INVALID_ARG = -1
+MF_E_UNSUPPORTED_SIZE = -2
+MF_E_TAU = -3
+MF_E_NONFINITE = -4
+MF_E_DEVICE = -5
+MF_E_WORKSPACE = -6
+MF_E_STATE = -7
+MF_PREC_FP64 = 0
+MF_PREC_FP32 = 1
+MF_NUM_KERNELS = 5
+KERNEL_NAMES = ("zpass", "yfwd", "xpass", "pkdraw", "yinv")
+
+# Symbols declared in include/mf.h, with their ctypes signatures.
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_double_pp = ctypes.POINTER(_c_double_p)
+
+
+class mf_chain_desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("n_bins", ctypes.c_int32),
+        ("box", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("chain_id", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+        ("sample_pk", ctypes.c_int32),
+        ("n_chains", ctypes.c_int32),
+    ]
+
+
+SIGNATURES = {
+    "mf_supported_n": (ctypes.c_int32, [ctypes.c_int32]),
+    "mf_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(mf_chain_desc),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_init_problem": (ctypes.c_int, [ctypes.POINTER(mf_chain_desc), _c_double_pp, _c_double_pp,
+                                       _c_double_pp, _c_double_pp, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "mf_gibbs_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "mf_gibbs_sweep_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            _c_double_p, ctypes.c_int32]),
+    "mf_get_chain_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
+                                          _c_double_p, ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.c_void_p]),
+    "mf_set_chain_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
+                                          _c_double_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "mf_get_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p]),
+    "mf_debug_run_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
+                                           ctypes.c_void_p]),
+    "mf_debug_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
+                                         ctypes.c_int32, ctypes.c_void_p]),
+    "mf_destroy_problem": (None, [ctypes.c_void_p]),
+    "mf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"mf status {status}: {message}")
+        self.status = status
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(the sampler has no non-HIP implementation)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, argtypes) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = argtypes
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != MF_OK:
+        raise MFError(status, load().mf_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def _ptr_array(arrays):
+    arr = (_c_double_p * len(arrays))()
+    for i, a in enumerate(arrays):
+        arr[i] = _dptr(a) if a is not None else _c_double_p()
+    return arr
+
+
+def make_desc(n: int, n_bins: int, box: float, seed: int, precision: str = "fp32",
+              tau: float = 0.0, chain_id: int = 0, sample_pk: bool = True,
+              n_chains: int = 1) -> mf_chain_desc:
+    prec = {"fp64": MF_PREC_FP64, "fp32": MF_PREC_FP32}[precision]
+    return mf_chain_desc(n=n, n_bins=n_bins, box=box, tau=tau, seed=seed, chain_id=chain_id,
+                         precision=prec, sample_pk=1 if sample_pk else 0, n_chains=n_chains)
+
+
+def mf_supported_n(n: int) -> bool:
+    return bool(load().mf_supported_n(n))
+
+
+def mf_workspace_bytes(desc: mf_chain_desc) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().mf_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def mf_init_problem(desc: mf_chain_desc, data: Sequence, noise_var: Sequence, pk_init: Sequence,
+                    s_init: Optional[Sequence], workspace_ptr: int, workspace_bytes: int,
+                    stream=None) -> int:
+    data = [_f64(a) for a in data]
+    noise_var = [_f64(a) for a in noise_var]
+    pk_init = [_f64(a) for a in pk_init]
+    s_list = None if s_init is None else [None if a is None else _f64(a) for a in s_init]
+    handle = ctypes.c_void_p()
+    _check(load().mf_init_problem(
+        ctypes.byref(desc), _ptr_array(data), _ptr_array(noise_var), _ptr_array(pk_init),
+        _ptr_array(s_list) if s_list is not None else None, ctypes.c_void_p(workspace_ptr),
+        workspace_bytes, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle)))
+    return handle.value
+
+
+def mf_gibbs_sweep(handle: int, n_sweeps: int, stream=None):
+    _check(load().mf_gibbs_sweep(ctypes.c_void_p(handle), n_sweeps,
+                                 ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mf_gibbs_sweep_timed(handle: int, n_sweeps: int, stream=None) -> np.ndarray:
+    out = np.zeros(MF_NUM_KERNELS, dtype=np.float64)
+    _check(load().mf_gibbs_sweep_timed(ctypes.c_void_p(handle), n_sweeps,
+                                       ctypes.c_void_p(_stream_ptr(stream)), _dptr(out),
+                                       MF_NUM_KERNELS))
+    return out
+
+
+def mf_get_chain_state(handle: int, chain: int, n: int, n_bins: int, stream=None,
+                       want_s: bool = True):
+    s = np.empty((n, n, n), dtype=np.float64) if want_s else None
+    pk = np.empty(n_bins, dtype=np.float64)
+    sweep = ctypes.c_uint64(0)
+    _check(load().mf_get_chain_state(ctypes.c_void_p(handle), chain,
+                                     _dptr(s) if s is not None else None, _dptr(pk),
+                                     ctypes.byref(sweep), ctypes.c_void_p(_stream_ptr(stream))))
+    return s, pk, sweep.value
+
+
+def mf_set_chain_state(handle: int, chain: int, s, pk, sweep: int, stream=None):
+    s = None if s is None else _f64(s)
+    pk = None if pk is None else _f64(pk)
+    _check(load().mf_set_chain_state(ctypes.c_void_p(handle), chain,
+                                     _dptr(s) if s is not None else None,
+                                     _dptr(pk) if pk is not None else None, sweep,
+                                     ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mf_get_tau(handle: int, chain: int = 0) -> float:
+    out = ctypes.c_double(0.0)
+    _check(load().mf_get_tau(ctypes.c_void_p(handle), chain, ctypes.byref(out)))
+    return out.value
+
+
+def mf_debug_run_kernel(handle: int, kernel: int, sweep: int, stream=None):
+    _check(load().mf_debug_run_kernel(ctypes.c_void_p(handle), kernel, sweep,
+                                      ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mf_debug_spectrum(handle: int, chain: int, n: int, buf: Optional[np.ndarray] = None,
+                      stream=None) -> np.ndarray:
+    """Read (buf None) or write (buf given) the half-complex working buffer,
+    shaped (N/2+1, N, N) complex [kz][ix][iy]."""
+    shape = (n // 2 + 1, n, n)
+    if buf is None:
+        out = np.empty(shape + (2,), dtype=np.float64)
+        _check(load().mf_debug_spectrum(ctypes.c_void_p(handle), chain, _dptr(out), 0,
+                                        ctypes.c_void_p(_stream_ptr(stream))))
+        return out[..., 0] + 1j * out[..., 1]
+    arr = np.ascontiguousarray(np.stack([buf.real, buf.imag], axis=-1), dtype=np.float64)
+    _check(load().mf_debug_spectrum(ctypes.c_void_p(handle), chain, _dptr(arr), 1,
+                                    ctypes.c_void_p(_stream_ptr(stream))))
+    return buf
+
+
+def mf_destroy_problem(handle: int):
+    if handle:
+        load().mf_destroy_problem(ctypes.c_void_p(handle))
+
+
+def mf_last_error() -> str:
+    return load().mf_last_error().decode()
+
+
+class Sampler:
+    """A problem on cuda:0 with a torch-owned workspace.
+
+    data, noise_var: (N, N, N) float64 arrays (or lists of them, one per
+    chain); noise_var = +inf marks unobserved voxels.  pk_init: initial P per
+    bin in physical units."""
+
+    def __init__(self, data, noise_var, pk_init, n_bins: int, box: float, seed: int,
+                 precision: str = "fp32", tau: float = 0.0, chain_id: int = 0,
+                 sample_pk: bool = True, s_init=None, device: str = "cuda"):
+        import torch
+        multi = isinstance(data, (list, tuple))
+        data_l = list(data) if multi else [data]
+        noise_l = list(noise_var) if multi else [noise_var]
+        pk_l = list(pk_init) if multi else [pk_init]
+        s_l = None if s_init is None else (list(s_init) if multi else [s_init])
+        self.n = int(np.shape(data_l[0])[0])
+        self.n_bins = n_bins
+        self.n_chains = len(data_l)
+        self.desc = make_desc(self.n, n_bins, box, seed, precision, tau, chain_id, sample_pk,
+                              self.n_chains)
+        self.workspace_bytes = mf_workspace_bytes(self.desc)
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        self._ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream()
+        self.handle = mf_init_problem(self.desc, data_l, noise_l, pk_l, s_l, self._ptr,
+                                      self.workspace_bytes, self.stream.cuda_stream)
+
+    def sweep(self, n_sweeps: int = 1):
+        mf_gibbs_sweep(self.handle, n_sweeps, self.stream.cuda_stream)
+
+    def sweep_timed(self, n_sweeps: int) -> np.ndarray:
+        return mf_gibbs_sweep_timed(self.handle, n_sweeps, self.stream.cuda_stream)
+
+    def state(self, chain: int = 0, want_s: bool = True):
+        return mf_get_chain_state(self.handle, chain, self.n, self.n_bins,
+                                  self.stream.cuda_stream, want_s)
+
+    def set_state(self, chain: int, s, pk, sweep: int):
+        mf_set_chain_state(self.handle, chain, s, pk, sweep, self.stream.cuda_stream)
+
+    def tau(self, chain: int = 0) -> float:
+        return mf_get_tau(self.handle, chain)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mf_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,583 @@
+// C ABI of the messenger-field Gibbs sampler (declarations and contract in
+// include/mf.h).  Host side: descriptor validation, workspace layout, FP64
+// set-up of the per-voxel messenger coefficients, tau, bin thresholds, mode
+// counts and twiddles, and the launch sequence of a sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "sweep_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+mf_status fail(mf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define MF_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(MF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool supported(int n) {
+  return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512;
+}
+
+template <typename R, int N>
+struct Geometry {
+  static constexpr int zp = mf::ZTile<R, N>::P;
+  static constexpr int ynpen = mf::YTile<R, N>::NPEN;
+  static constexpr int xp = mf::XTile<R, N>::P;
+  static constexpr int xnwaves = mf::XTile<R, N>::NWAVES;
+};
+
+struct Shape {
+  int zp, ynpen, xp, xnwaves;
+};
+
+template <typename R>
+Shape shape_of(int n) {
+  switch (n) {
+#define MF_SHAPE(NN) \
+  case NN: return Shape{Geometry<R, NN>::zp, Geometry<R, NN>::ynpen, Geometry<R, NN>::xp, Geometry<R, NN>::xnwaves};
+    MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(64) MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
+#undef MF_SHAPE
+  }
+  return Shape{0, 0, 0, 0};
+}
+
+struct Layout {
+  size_t tw, qthr, counts, tau, pk, table, status, partials, alpha, beta, spec, staging, total;
+  size_t spec_elems, spec_stride;
+  int n_wg_x;
+};
+
+Layout make_layout(const mf_chain_desc& d) {
+  const bool fp64 = d.precision == MF_PREC_FP64;
+  const size_t rs = fp64 ? 8 : 4;
+  const size_t n = static_cast<size_t>(d.n), m = n * n * n, nb = d.n_bins, nc = d.n_chains;
+  const Shape sh = fp64 ? shape_of<double>(d.n) : shape_of<float>(d.n);
+  Layout L{};
+  L.spec_elems = (n / 2 + 1) * n * n;
+  L.spec_stride = align_up(L.spec_elems * 2 * rs) / (2 * rs);
+  L.n_wg_x = static_cast<int>((n / 2 + 1) * (n / sh.xp));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.tw = take(n * 2 * rs);
+  L.qthr = take(nb * 4);
+  L.counts = take(nb * 8);
+  L.tau = take(nc * 8);
+  L.pk = take(nc * nb * 8);
+  L.table = take(nc * nb * 2 * rs);
+  L.status = take(nc * 4);
+  L.partials = take(nc * static_cast<size_t>(L.n_wg_x) * nb * 8);
+  L.alpha = take(nc * m * rs);
+  L.beta = take(nc * m * rs);
+  L.spec = take(nc * L.spec_stride * 2 * rs);
+  L.staging = take(m * rs);
+  L.total = off;
+  return L;
+}
+
+mf_status check_desc(const mf_chain_desc* d) {
+  if (!d) return fail(MF_E_INVALID_ARG, "descriptor is NULL");
+  if (!supported(d->n))
+    return fail(MF_E_UNSUPPORTED_SIZE, "grid side %d unsupported (power of two in [8, 512])", d->n);
+  if (d->n_bins < 1 || d->n_bins > 1024)
+    return fail(MF_E_INVALID_ARG, "n_bins %d outside [1, 1024]", d->n_bins);
+  if (!(d->box > 0.0) || !std::isfinite(d->box))
+    return fail(MF_E_INVALID_ARG, "box side must be positive and finite");
+  if (d->precision != MF_PREC_FP64 && d->precision != MF_PREC_FP32)
+    return fail(MF_E_INVALID_ARG, "unknown precision %d", d->precision);
+  if (d->n_chains < 1 || d->n_chains > 4096)
+    return fail(MF_E_INVALID_ARG, "n_chains %d outside [1, 4096]", d->n_chains);
+  if (d->sample_pk != 0 && d->sample_pk != 1)
+    return fail(MF_E_INVALID_ARG, "sample_pk must be 0 or 1");
+  if (std::isnan(d->tau)) return fail(MF_E_INVALID_ARG, "tau is NaN");
+  return MF_OK;
+}
+
+// Smallest q of every bin: Q_0 = 1, Q_b = ceil(3 b^2 N^2 / (4 nb^2)) (exact).
+std::vector<int32_t> bin_thresholds(int n, int nb) {
+  std::vector<int32_t> q(nb);
+  q[0] = 1;
+  const unsigned long long den = 4ull * nb * nb;
+  for (int b = 1; b < nb; ++b) {
+    const unsigned long long num = 3ull * b * b * static_cast<unsigned long long>(n) * n;
+    q[b] = static_cast<int32_t>((num + den - 1) / den);
+  }
+  return q;
+}
+
+// Full-grid modes per bin, counted over the half grid with weights 1 on the
+// kz = 0 and kz = N/2 planes and 2 elsewhere.
+std::vector<double> bin_counts(int n, int nb, const std::vector<int32_t>& qthr) {
+  std::vector<long long> cnt(nb, 0);
+  const int h = n / 2;
+  std::vector<int> m2(n);
+  for (int i = 0; i < n; ++i) {
+    const int m = i <= h ? i : i - n;
+    m2[i] = m * m;
+  }
+  for (int ix = 0; ix < n; ++ix)
+    for (int iy = 0; iy < n; ++iy)
+      for (int kz = 0; kz <= h; ++kz) {
+        const int q = m2[ix] + m2[iy] + kz * kz;
+        if (q == 0) continue;
+        const int b = static_cast<int>(std::upper_bound(qthr.begin(), qthr.end(), q) - qthr.begin()) - 1;
+        cnt[b] += (kz == 0 || kz == h) ? 1 : 2;
+      }
+  return std::vector<double>(cnt.begin(), cnt.end());
+}
+
+// exp(-2 pi i j / N) in FP64 from long-double angles.
+std::vector<double> twiddles(int n) {
+  std::vector<double> tw(2 * n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < n; ++j) {
+    const long double ang = 2.0L * pi * j / n;
+    double c = static_cast<double>(cosl(ang)), s = -static_cast<double>(sinl(ang));
+    if (std::fabs(c) < 1e-18) c = 0.0;
+    if (std::fabs(s) < 1e-18) s = 0.0;
+    tw[2 * j] = c;
+    tw[2 * j + 1] = s;
+  }
+  return tw;
+}
+
+}  // namespace
+
+struct mf_problem {
+  mf_chain_desc desc;
+  Layout L;
+  Shape sh;
+  char* ws;
+  std::vector<double> tau;
+  uint64_t sweep;
+  bool fp64() const { return desc.precision == MF_PREC_FP64; }
+};
+
+namespace {
+
+template <typename R>
+mf::SweepArgs<R> args_of(const mf_problem* p) {
+  mf::SweepArgs<R> a{};
+  char* ws = p->ws;
+  a.spec = reinterpret_cast<mf::cx<R>*>(ws + p->L.spec);
+  a.alpha = reinterpret_cast<const R*>(ws + p->L.alpha);
+  a.beta = reinterpret_cast<const R*>(ws + p->L.beta);
+  a.staging = reinterpret_cast<R*>(ws + p->L.staging);
+  a.tau = reinterpret_cast<const double*>(ws + p->L.tau);
+  a.pk = reinterpret_cast<double*>(ws + p->L.pk);
+  a.table = reinterpret_cast<R*>(ws + p->L.table);
+  a.partials = reinterpret_cast<double*>(ws + p->L.partials);
+  a.qthr = reinterpret_cast<const int32_t*>(ws + p->L.qthr);
+  a.counts = reinterpret_cast<const double*>(ws + p->L.counts);
+  a.tw = reinterpret_cast<const mf::cx<R>*>(ws + p->L.tw);
+  a.status = reinterpret_cast<uint32_t*>(ws + p->L.status);
+  a.spec_stride = p->L.spec_stride;
+  a.m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  a.nb = p->desc.n_bins;
+  a.n_wg_x = p->L.n_wg_x;
+  a.staging_chain = 0;
+  a.sample_pk = p->desc.sample_pk;
+  a.sweep = static_cast<uint32_t>(p->sweep);
+  a.chain0 = p->desc.chain_id;
+  a.key0 = static_cast<uint32_t>(p->desc.seed);
+  a.key1 = static_cast<uint32_t>(p->desc.seed >> 32);
+  return a;
+}
+
+enum KernelId { kZ = 0, kYF = 1, kX = 2, kPk = 3, kYI = 4, kZSet = 10, kZGet = 11, kTable = 12 };
+
+template <typename R, int N>
+void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
+  using ZT = mf::ZTile<R, N>;
+  using YT = mf::YTile<R, N>;
+  using XT = mf::XTile<R, N>;
+  const dim3 zgrid(N / ZT::P, N, nch), zgrid1(N / ZT::P, N, 1);
+  const dim3 ygrid((N / 2 + 1) * N / YT::NPEN, 1, nch);
+  const dim3 xgrid(N / XT::P, N / 2 + 1, nch);
+  switch (id) {
+    case kZ:
+      hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZSweep>), zgrid, dim3(ZT::NT), 0, st, a);
+      break;
+    case kZSet:
+      hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZSetState>), zgrid1, dim3(ZT::NT), 0, st, a);
+      break;
+    case kZGet:
+      hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZGetState>), zgrid1, dim3(ZT::NT), 0, st, a);
+      break;
+    case kYF:
+      hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), ygrid, dim3(YT::NT), 0, st, a);
+      break;
+    case kYI:
+      hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>), ygrid, dim3(YT::NT), 0, st, a);
+      break;
+    case kX: {
+      const size_t dyn = XT::NWAVES * a.nb * sizeof(double) + 2 * a.nb * sizeof(R) + a.nb * 4;
+      hipLaunchKernelGGL((mf::xpass_kernel<R, N>), xgrid, dim3(XT::NT), dyn, st, a);
+      break;
+    }
+    case kPk:
+      hipLaunchKernelGGL((mf::pk_draw_kernel<R>), dim3(a.nb, nch), dim3(mf::kPkThreads), 0, st, a);
+      break;
+    case kTable:
+      hipLaunchKernelGGL((mf::pk_table_kernel<R>), dim3((a.nb + 63) / 64, nch), dim3(64), 0, st, a);
+      break;
+  }
+}
+
+template <typename R>
+void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st) {
+  switch (n) {
+    case 8: launch_n<R, 8>(id, a, nch, st); break;
+    case 16: launch_n<R, 16>(id, a, nch, st); break;
+    case 32: launch_n<R, 32>(id, a, nch, st); break;
+    case 64: launch_n<R, 64>(id, a, nch, st); break;
+    case 128: launch_n<R, 128>(id, a, nch, st); break;
+    case 256: launch_n<R, 256>(id, a, nch, st); break;
+    case 512: launch_n<R, 512>(id, a, nch, st); break;
+  }
+}
+
+mf_status launch_checked(mf_problem* p, int id, uint64_t sweep, int staging_chain,
+                         hipStream_t st) {
+  const int nch = p->desc.n_chains;
+  if (p->fp64()) {
+    auto a = args_of<double>(p);
+    a.sweep = static_cast<uint32_t>(sweep);
+    a.staging_chain = staging_chain;
+    launch<double>(id, a, p->desc.n, nch, st);
+  } else {
+    auto a = args_of<float>(p);
+    a.sweep = static_cast<uint32_t>(sweep);
+    a.staging_chain = staging_chain;
+    launch<float>(id, a, p->desc.n, nch, st);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MF_E_DEVICE, "kernel %d launch failed: %s", id, hipGetErrorString(e));
+  return MF_OK;
+}
+
+const int kSweepOrder[MF_NUM_KERNELS] = {kZ, kYF, kX, kPk, kYI};
+
+// Host FP64 -> device R copy through a temporary host buffer.
+mf_status upload_real(mf_problem* p, void* dst, const double* src, size_t count, hipStream_t st) {
+  if (p->fp64()) {
+    MF_HIP(hipMemcpyAsync(dst, src, count * 8, hipMemcpyHostToDevice, st));
+    MF_HIP(hipStreamSynchronize(st));
+  } else {
+    std::vector<float> tmp(count);
+    for (size_t i = 0; i < count; ++i) tmp[i] = static_cast<float>(src[i]);
+    MF_HIP(hipMemcpyAsync(dst, tmp.data(), count * 4, hipMemcpyHostToDevice, st));
+    MF_HIP(hipStreamSynchronize(st));
+  }
+  return MF_OK;
+}
+
+mf_status download_real(mf_problem* p, double* dst, const void* src, size_t count, hipStream_t st) {
+  if (p->fp64()) {
+    MF_HIP(hipMemcpyAsync(dst, src, count * 8, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+  } else {
+    std::vector<float> tmp(count);
+    MF_HIP(hipMemcpyAsync(tmp.data(), src, count * 4, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < count; ++i) dst[i] = tmp[i];
+  }
+  return MF_OK;
+}
+
+mf_status set_state(mf_problem* p, int chain, const double* s, const double* pk, hipStream_t st) {
+  const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  const size_t rs = p->fp64() ? 8 : 4;
+  if (s) {
+    mf_status r = upload_real(p, p->ws + p->L.staging, s, m, st);
+    if (r != MF_OK) return r;
+    r = launch_checked(p, kZSet, p->sweep, chain, st);
+    if (r != MF_OK) return r;
+  }
+  if (pk) {
+    const double vc = std::pow(p->desc.box / p->desc.n, 3);
+    std::vector<double> pg(p->desc.n_bins);
+    for (int b = 0; b < p->desc.n_bins; ++b) {
+      if (!std::isfinite(pk[b]) || pk[b] < 0.0)
+        return fail(MF_E_NONFINITE, "P of bin %d is negative or not finite", b);
+      pg[b] = pk[b] / vc;
+    }
+    MF_HIP(hipMemcpyAsync(p->ws + p->L.pk + static_cast<size_t>(chain) * p->desc.n_bins * 8,
+                          pg.data(), pg.size() * 8, hipMemcpyHostToDevice, st));
+    MF_HIP(hipStreamSynchronize(st));
+    mf_status r = launch_checked(p, kTable, p->sweep, chain, st);
+    if (r != MF_OK) return r;
+  }
+  (void)rs;
+  MF_HIP(hipStreamSynchronize(st));
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mf_supported_n(int32_t n) { return supported(n) ? 1 : 0; }
+
+mf_status mf_workspace_bytes(const mf_chain_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(MF_E_INVALID_ARG, "bytes is NULL");
+  const mf_status st = check_desc(desc);
+  if (st != MF_OK) return st;
+  *bytes = make_layout(*desc).total;
+  return MF_OK;
+}
+
+mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
+                          const double* const* noise_var, const double* const* pk_init,
+                          const double* const* s_init, void* workspace, size_t workspace_bytes,
+                          void* stream, mf_problem** out) {
+  if (!out) return fail(MF_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  mf_status st = check_desc(desc);
+  if (st != MF_OK) return st;
+  if (!data || !noise_var || !pk_init) return fail(MF_E_INVALID_ARG, "input arrays are NULL");
+  const int n = desc->n, nb = desc->n_bins, nch = desc->n_chains;
+  for (int c = 0; c < nch; ++c)
+    if (!data[c] || !noise_var[c] || !pk_init[c])
+      return fail(MF_E_INVALID_ARG, "input array of chain %d is NULL", c);
+  const Layout L = make_layout(*desc);
+  if (!workspace) return fail(MF_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(MF_E_WORKSPACE, "workspace is not %zu-byte aligned", kAlign);
+  if (workspace_bytes < L.total)
+    return fail(MF_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+
+  const size_t m = static_cast<size_t>(n) * n * n;
+  const double vc = std::pow(desc->box / n, 3);
+  // tau per chain and input checks (Sec. 2: 0 < tau <= N_i on observed voxels)
+  std::vector<double> tau(nch);
+  for (int c = 0; c < nch; ++c) {
+    double tmin = std::numeric_limits<double>::infinity();
+    size_t n_obs = 0;
+    for (size_t i = 0; i < m; ++i) {
+      const double nv = noise_var[c][i];
+      if (std::isinf(nv) && nv > 0) continue;
+      if (!(nv > 0.0) || !std::isfinite(nv))
+        return fail(MF_E_NONFINITE, "chain %d voxel %zu: noise variance %g not > 0", c, i, nv);
+      if (!std::isfinite(data[c][i]))
+        return fail(MF_E_NONFINITE, "chain %d voxel %zu: data not finite", c, i);
+      tmin = std::min(tmin, nv);
+      ++n_obs;
+    }
+    if (n_obs == 0) return fail(MF_E_INVALID_ARG, "chain %d has no observed voxel", c);
+    if (desc->tau > 0.0) {
+      if (desc->tau > tmin)
+        return fail(MF_E_TAU, "tau %g exceeds the smallest observed noise variance %g of chain %d",
+                    desc->tau, tmin, c);
+      tau[c] = desc->tau;
+    } else {
+      tau[c] = tmin;
+    }
+    for (int b = 0; b < nb; ++b)
+      if (!std::isfinite(pk_init[c][b]) || pk_init[c][b] < 0.0)
+        return fail(MF_E_NONFINITE, "chain %d: initial P of bin %d negative or not finite", c, b);
+  }
+
+  mf_problem* p = new mf_problem{};
+  p->desc = *desc;
+  p->L = L;
+  p->sh = desc->precision == MF_PREC_FP64 ? shape_of<double>(n) : shape_of<float>(n);
+  p->ws = static_cast<char*>(workspace);
+  p->tau = tau;
+  p->sweep = 0;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+
+  auto cleanup = [&](mf_status r) {
+    delete p;
+    return r;
+  };
+  // constant tables
+  const std::vector<int32_t> qthr = bin_thresholds(n, nb);
+  const std::vector<double> counts = bin_counts(n, nb, qthr);
+  const std::vector<double> tw = twiddles(n);
+  if ((st = upload_real(p, p->ws + L.tw, tw.data(), tw.size(), hs)) != MF_OK) return cleanup(st);
+  if (hipMemcpyAsync(p->ws + L.qthr, qthr.data(), nb * 4, hipMemcpyHostToDevice, hs) != hipSuccess ||
+      hipMemcpyAsync(p->ws + L.counts, counts.data(), nb * 8, hipMemcpyHostToDevice, hs) != hipSuccess ||
+      hipMemcpyAsync(p->ws + L.tau, tau.data(), nch * 8, hipMemcpyHostToDevice, hs) != hipSuccess ||
+      hipMemsetAsync(p->ws + L.status, 0, nch * 4, hs) != hipSuccess ||
+      hipMemsetAsync(p->ws + L.partials, 0, static_cast<size_t>(nch) * L.n_wg_x * nb * 8, hs) != hipSuccess ||
+      hipStreamSynchronize(hs) != hipSuccess)
+    return cleanup(fail(MF_E_DEVICE, "uploading tables failed"));
+  // messenger coefficients in FP64: alpha = 1 - tau/N, beta = tau d / N
+  const size_t rs = p->fp64() ? 8 : 4;
+  std::vector<double> coef(m);
+  for (int c = 0; c < nch; ++c) {
+    for (size_t i = 0; i < m; ++i) {
+      const double nv = noise_var[c][i];
+      coef[i] = (std::isinf(nv)) ? 1.0 : 1.0 - tau[c] / nv;
+    }
+    if ((st = upload_real(p, p->ws + L.alpha + c * m * rs, coef.data(), m, hs)) != MF_OK)
+      return cleanup(st);
+    for (size_t i = 0; i < m; ++i) {
+      const double nv = noise_var[c][i];
+      coef[i] = (std::isinf(nv)) ? 0.0 : tau[c] * data[c][i] / nv;
+    }
+    if ((st = upload_real(p, p->ws + L.beta + c * m * rs, coef.data(), m, hs)) != MF_OK)
+      return cleanup(st);
+  }
+  // initial state
+  if (hipMemsetAsync(p->ws + L.spec, 0, static_cast<size_t>(nch) * L.spec_stride * 2 * rs, hs) !=
+      hipSuccess)
+    return cleanup(fail(MF_E_DEVICE, "clearing the spectrum failed"));
+  for (int c = 0; c < nch; ++c) {
+    const double* s0 = (s_init && s_init[c]) ? s_init[c] : nullptr;
+    if (s0)
+      for (size_t i = 0; i < m; ++i)
+        if (!std::isfinite(s0[i])) return cleanup(fail(MF_E_NONFINITE, "s_init not finite"));
+    if ((st = set_state(p, c, s0, pk_init[c], hs)) != MF_OK) return cleanup(st);
+  }
+  (void)vc;
+  *out = p;
+  return MF_OK;
+}
+
+mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (n_sweeps < 0) return fail(MF_E_INVALID_ARG, "negative sweep count");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < n_sweeps; ++i) {
+    for (int k = 0; k < MF_NUM_KERNELS; ++k) {
+      const mf_status st = launch_checked(p, kSweepOrder[k], p->sweep, 0, hs);
+      if (st != MF_OK) return st;
+    }
+    ++p->sweep;
+  }
+  return MF_OK;
+}
+
+mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, double* kernel_ms,
+                               int32_t n_kernels) {
+  if (!p || !kernel_ms || n_kernels < 0) return fail(MF_E_INVALID_ARG, "bad argument");
+  if (n_sweeps <= 0) return fail(MF_E_INVALID_ARG, "need at least one sweep");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  std::vector<hipEvent_t> ev(static_cast<size_t>(n_sweeps) * (MF_NUM_KERNELS + 1));
+  for (auto& e : ev) MF_HIP(hipEventCreate(&e));
+  mf_status st = MF_OK;
+  for (int i = 0; i < n_sweeps && st == MF_OK; ++i) {
+    hipEvent_t* e = &ev[static_cast<size_t>(i) * (MF_NUM_KERNELS + 1)];
+    MF_HIP(hipEventRecord(e[0], hs));
+    for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k) {
+      st = launch_checked(p, kSweepOrder[k], p->sweep, 0, hs);
+      if (st == MF_OK) MF_HIP(hipEventRecord(e[k + 1], hs));
+    }
+    ++p->sweep;
+  }
+  if (st == MF_OK) {
+    MF_HIP(hipStreamSynchronize(hs));
+    double sum[MF_NUM_KERNELS] = {0};
+    for (int i = 0; i < n_sweeps; ++i)
+      for (int k = 0; k < MF_NUM_KERNELS; ++k) {
+        float ms = 0.f;
+        hipEvent_t* e = &ev[static_cast<size_t>(i) * (MF_NUM_KERNELS + 1)];
+        MF_HIP(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+        sum[k] += ms;
+      }
+    for (int k = 0; k < std::min<int>(n_kernels, MF_NUM_KERNELS); ++k) kernel_ms[k] = sum[k] / n_sweeps;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return st;
+}
+
+mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double* pk_out,
+                             uint64_t* sweep_out, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  if (s_out) {
+    mf_status st = launch_checked(p, kZGet, p->sweep, chain, hs);
+    if (st != MF_OK) return st;
+    if ((st = download_real(p, s_out, p->ws + p->L.staging, m, hs)) != MF_OK) return st;
+  }
+  if (pk_out) {
+    const int nb = p->desc.n_bins;
+    MF_HIP(hipMemcpyAsync(pk_out, p->ws + p->L.pk + static_cast<size_t>(chain) * nb * 8, nb * 8,
+                          hipMemcpyDeviceToHost, hs));
+    MF_HIP(hipStreamSynchronize(hs));
+    const double vc = std::pow(p->desc.box / p->desc.n, 3);
+    for (int b = 0; b < nb; ++b) pk_out[b] *= vc;
+  }
+  uint32_t status = 0;
+  MF_HIP(hipMemcpyAsync(&status, p->ws + p->L.status + chain * 4, 4, hipMemcpyDeviceToHost, hs));
+  MF_HIP(hipStreamSynchronize(hs));
+  if (sweep_out) *sweep_out = p->sweep;
+  if (status) return fail(MF_E_NONFINITE, "chain %d: non-finite shell sum or P draw on device", chain);
+  return MF_OK;
+}
+
+mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, const double* pk,
+                             uint64_t sweep, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  if (s)
+    for (size_t i = 0; i < m; ++i)
+      if (!std::isfinite(s[i])) return fail(MF_E_NONFINITE, "s not finite at %zu", i);
+  p->sweep = sweep;
+  return set_state(p, chain, s, pk, static_cast<hipStream_t>(stream));
+}
+
+mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out) {
+  if (!p || !tau_out) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  *tau_out = p->tau[chain];
+  return MF_OK;
+}
+
+mf_status mf_debug_run_kernel(mf_problem* p, int32_t kernel, uint64_t sweep, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (kernel < 0 || kernel >= MF_NUM_KERNELS) return fail(MF_E_INVALID_ARG, "bad kernel id");
+  return launch_checked(p, kSweepOrder[kernel], sweep, 0, static_cast<hipStream_t>(stream));
+}
+
+mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t to_device,
+                            void* stream) {
+  if (!p || !buf) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const size_t count = 2 * p->L.spec_elems;
+  const size_t rs = p->fp64() ? 8 : 4;
+  char* dev = p->ws + p->L.spec + static_cast<size_t>(chain) * p->L.spec_stride * 2 * rs;
+  if (to_device) return upload_real(p, dev, buf, count, hs);
+  return download_real(p, buf, dev, count, hs);
+}
+
+void mf_destroy_problem(mf_problem* p) { delete p; }
+
+const char* mf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
