@@ -1,0 +1,201 @@
+"""Benchmark: Gibbs sweeps/s of the messenger-field sampler at 256^3, FP32
+fields and FFTs with FP64 shell sums and inverse-gamma draws, on one GPU.
+
+A step is one full Gibbs sweep (messenger draw, forward FFT, signal draw,
+shell power, P(k) draw, inverse FFT) of one chain over the synthetic
+survey-like problem (sphere of radius 0.45 L minus a 30-degree wedge, noise
+1/(nbar sel(r) V_cell)).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus N > 1 is refused: the sampler runs one chain
+per GPU and this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def source_digest() -> str:
+    """Digest of the kernel sources; stored beside profiled counters so that
+    traffic figures are only reported for the code they were measured on."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1402_1763_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, real_bytes: int, n_bins: int, n_wg_x: int) -> dict:
+    """Bytes each sweep kernel must move: the half-complex field is read and
+    written once per pass, the z-pass also reads the two messenger
+    coefficients per voxel; the P draw reads the shell partials."""
+    m = n ** 3
+    spec = (n // 2 + 1) * n * n * 2 * real_bytes
+    return {
+        "zpass": 2 * spec + 2 * m * real_bytes,
+        "yfwd": 2 * spec,
+        "xpass": 2 * spec + n_wg_x * n_bins * 8,
+        "pkdraw": n_wg_x * n_bins * 8 + n_bins * (16 + 2 * real_bytes),
+        "yinv": 2 * spec,
+    }
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if recorded for
+    the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(workload, {}).get(kernel)
+    if not entry or entry.get("source_digest") != source_digest():
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, pb, max_seconds: float = 30.0):
+    """The FP64 oracle timed on the host cores over a bounded sample."""
+    ncores = len(os.sched_getaffinity(0))
+    os.environ["ORACLE_FFT_WORKERS"] = str(ncores)
+    from oracle import sampler
+    prob = sampler.make_problem(pb["data"], pb["noise_var"], w.n_bins, w.box, w.rng_seed)
+    st = sampler.State(s=np.zeros((w.n,) * 3), p_grid=pb["pk_init"] / w.cell_volume)
+    t0 = time.perf_counter()
+    st = sampler.sweep(prob, st)                      # warm-up sweep
+    warm = time.perf_counter() - t0
+    n_timed = max(1, min(3, int(max_seconds / max(warm, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    for _ in range(n_timed):
+        st = sampler.sweep(prob, st)
+    dt = time.perf_counter() - t0
+    return {"value": n_timed / dt, "unit": "sweeps/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{n_timed} FP64 oracle sweeps of the same {w.n}^3 problem after one "
+                      f"warm-up sweep (numpy Philox single-threaded, scipy.fft with "
+                      f"{ncores} workers)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="gibbs-256^3-fp32-survey")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (calibrates "
+                         "the HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(args.calibrate_copy * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written":
+                          dst.numel() * 4, "launches": 10}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: the sampler runs on one GPU "
+              "(independent chains shard one per GPU; no multi-GPU figure is measured)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1402_1763_amd import binding, workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    pb = workloads.make_problem(w)
+    torch.cuda.set_device(0)
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision=w.precision)
+    stream = torch.cuda.current_stream()
+    smp.sweep(args.warmup)
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    smp.sweep(args.steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t_wall
+    ms_total = start.elapsed_time(stop)
+    ms_per_step = ms_total / args.steps
+
+    _, pk, n_done = smp.state(want_s=False)
+    assert np.all(np.isfinite(pk)) and n_done == args.warmup + args.steps
+
+    real_bytes = 8 if w.precision == "fp64" else 4
+    n = w.n
+    xp = {4: min(n, 8192 // n), 8: min(n, 4096 // n)}[real_bytes]
+    n_wg_x = (n // 2 + 1) * (n // xp)
+    alg = algorithmic_bytes(n, real_bytes, w.n_bins, n_wg_x)
+    sweep_bytes = sum(alg.values())
+
+    roofline = None
+    kernel_ms = None
+    if not args.no_kernel_timing:
+        kms = smp.sweep_timed(min(args.steps, 200))
+        kernel_ms = dict(zip(binding.KERNEL_NAMES, [float(x) for x in kms]))
+        dom = max(kernel_ms, key=kernel_ms.get)
+        achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
+        traffic = load_traffic(dom, w.name)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "kernel": dom,
+                    "algorithmic_bytes_per_launch": alg[dom],
+                    "kernel_ms": {k: round(v, 5) for k, v in kernel_ms.items()}}
+    smp.close()
+
+    out = {
+        "metric": "Gibbs sweeps/s at 256^3 FP32 (and % HBM roofline) vs plain FP64 sweep",
+        "value": round(1000.0 / ms_per_step, 2),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "box": w.box, "n_bins": w.n_bins,
+                   "precision": "FP32 fields/FFTs/draws, FP64 shell sums and P draws",
+                   "mask": "sphere r<0.45L minus seeded 30deg wedge",
+                   "chains": 1,
+                   "sweep_bytes_algorithmic": sweep_bytes,
+                   "sweep_hbm_frac": round(sweep_bytes / (ms_per_step * 1e-3) / 1e9
+                                           / HBM_PEAK_GBS, 4),
+                   "wall_s_timed_region": round(wall_s, 4)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, pb)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

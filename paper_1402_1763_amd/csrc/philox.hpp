@@ -49,13 +49,16 @@ __device__ __forceinline__ R u23(uint32_t x) {
   return (static_cast<R>(x >> 9) + R(0.5)) * R(1.1920928955078125e-07);  // 2^-23
 }
 
-// Box-Muller pair from two words, in the precision R.
+// Box-Muller pair from two words, in the precision R.  The FP32 form uses the
+// hardware transcendentals: v_log_f32 is log2, v_sin_f32 / v_cos_f32 take
+// their argument in revolutions (sin(2 pi x)), so theta = 2 pi U23 needs no
+// range reduction; all are accurate to a few ulp on (0, 1).
 __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, float& g0, float& g1) {
-  const float r = sqrtf(-2.0f * logf(u23<float>(xa)));
-  float s, c;
-  sincospif(2.0f * u23<float>(xb), &s, &c);
-  g0 = r * c;
-  g1 = r * s;
+  constexpr float kMinus2Ln2 = -1.38629436111989061883f;   // -2 ln 2
+  const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u23<float>(xa)));
+  const float turn = u23<float>(xb);
+  g0 = r * __builtin_amdgcn_cosf(turn);
+  g1 = r * __builtin_amdgcn_sinf(turn);
 }
 
 __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, double& g0, double& g1) {

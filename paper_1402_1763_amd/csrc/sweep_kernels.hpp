@@ -5,7 +5,7 @@
 //   spec         [kz][ix][iy]  cx<R>  half-complex working field, kz <= N/2
 //   table        [b][2]        R      per-bin (A_b, B_b) of the signal draw
 //   pk           [b]           double P_b in grid units (variance per voxel)
-//   partials     [wg][b]       double per-workgroup shell sums of the x-pass
+//   partials     [b][wg]       double per-workgroup shell sums of the x-pass
 // Between sweeps `spec` holds s transformed along z only, Y = DFT_z(s) / N
 // (a real-to-half-complex DFT of each z pencil), so keeping the state costs
 // no extra pass.
@@ -37,7 +37,7 @@ struct SweepArgs {
   const double* tau;      // [chain]
   double* pk;             // [chain][nb]
   R* table;               // [chain][nb][2]
-  double* partials;       // [chain][n_wg_x][nb]
+  double* partials;       // [chain][nb][n_wg_x]
   const int32_t* qthr;    // [nb] smallest q of every bin
   const double* counts;   // [nb] full-grid modes per bin
   const cx<R>* tw;        // [N] exp(-2 pi i j / N)
@@ -398,11 +398,11 @@ xpass_kernel(SweepArgs<R> a) {
     spec[static_cast<size_t>(ix) * N + iy0 + col] = lds[col * PSTR + ix];
   }
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-  double* part = a.partials + (static_cast<size_t>(c) * a.n_wg_x + wg) * nb;
+  double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
   for (int b = tid; b < nb; b += NT) {
     double s = 0.0;
     for (int w = 0; w < T::NWAVES; ++w) s += hist[w * nb + b];
-    part[b] = s;
+    part[static_cast<size_t>(b) * a.n_wg_x] = s;
   }
 }
 
@@ -425,9 +425,9 @@ template <typename R>
 __global__ void __launch_bounds__(kPkThreads) pk_draw_kernel(SweepArgs<R> a) {
   __shared__ double red[kPkThreads];
   const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-  const double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * a.nb + b;
+  const double* part = a.partials + (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x;
   double s = 0.0;
-  for (int w = tid; w < a.n_wg_x; w += kPkThreads) s += part[static_cast<size_t>(w) * a.nb];
+  for (int w = tid; w < a.n_wg_x; w += kPkThreads) s += part[w];
   red[tid] = s;
   __syncthreads();
   for (int h = kPkThreads / 2; h > 0; h >>= 1) {
