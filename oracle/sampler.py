@@ -102,31 +102,30 @@ def make_problem(data, noise_var, n_bins: int, box: float, seed: int, chain: int
 
 # ---------------------------------------------------------------- draws
 def messenger_normals(n: int, seed: int, chain: int, sweep: int) -> np.ndarray:
-    """G(0,1) for every voxel (ix, iy, iz): one Philox call per 4 consecutive iz,
-    counter ((ix N + iy) N/4 + iz // 4, sweep, 0, chain), lanes in iz order."""
+    """G(0,1) for every voxel (ix, iy, iz).  One Philox call per voxel quad
+    iz in {c, c + N/4, c + N/2, c + 3N/4} of a z pencil, counter
+    ((ix N + iy) N/4 + c, sweep, 0, chain); the quad takes the call's four
+    normals in order (cos and sin of the first word pair, then of the second)."""
+    q4 = n // 4
     ix = np.arange(n, dtype=np.uint64)[:, None, None]
     iy = np.arange(n, dtype=np.uint64)[None, :, None]
-    g = np.arange(n // 4, dtype=np.uint64)[None, None, :]
-    w0 = (ix * np.uint64(n) + iy) * np.uint64(n // 4) + g
+    c = np.arange(q4, dtype=np.uint64)[None, None, :]
+    w0 = (ix * np.uint64(n) + iy) * np.uint64(q4) + c
     lanes = philox.normals4(w0, sweep, philox.PHASE_MESSENGER, chain, seed)
-    return np.stack(lanes, axis=-1).reshape(n, n, n)
+    return np.concatenate(lanes, axis=2)          # iz = j * N/4 + c
 
 
 def signal_normals(n: int, seed: int, chain: int, sweep: int):
-    """(G_re, G_im) for every half-grid mode (ix, iy, iz), iz <= n/2: one Philox
-    call per pair of consecutive ix, counter ((iz N + iy) N/2 + ix // 2, sweep,
-    1, chain); even ix takes the first word pair, odd ix the second."""
+    """(G_re, G_im) for every half-grid mode (ix, iy, iz), iz <= n/2.  One Philox
+    call per mode pair (ix, ix + N/2), ix < N/2, counter ((iz N + iy) N/2 + ix,
+    sweep, 1, chain); ix < N/2 takes the first word pair, ix + N/2 the second."""
     h = n // 2
     p = np.arange(h, dtype=np.uint64)[:, None, None]
     iy = np.arange(n, dtype=np.uint64)[None, :, None]
     iz = np.arange(h + 1, dtype=np.uint64)[None, None, :]
     w0 = (iz * np.uint64(n) + iy) * np.uint64(h) + p
     ga, gb, gc, gd = philox.normals4(w0, sweep, philox.PHASE_SIGNAL, chain, seed)
-    g_re = np.empty((n, n, h + 1))
-    g_im = np.empty((n, n, h + 1))
-    g_re[0::2], g_im[0::2] = ga, gb
-    g_re[1::2], g_im[1::2] = gc, gd
-    return g_re, g_im
+    return np.concatenate([ga, gc], axis=0), np.concatenate([gb, gd], axis=0)
 
 
 # ---------------------------------------------------------------- steps

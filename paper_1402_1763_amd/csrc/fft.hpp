@@ -1,17 +1,27 @@
-// LDS-resident batched pencil FFTs for gfx950.
+// Register-resident batched pencil FFTs for gfx950.
 //
-// A workgroup holds a tile of NPEN pencils of length N in LDS (pencil p at
-// buf + p * PSTR) and transforms all of them with a Stockham autosort
-// schedule: each stage reads every butterfly's inputs into registers,
-// applies the inter-stage twiddles, runs an unrolled radix-R DFT in
-// registers, and writes the outputs back in place after a barrier.  With
-// E = NPEN * N elements and NT threads, every thread owns E / NT elements in
-// every stage whatever the radix.
+// A workgroup transforms NPEN pencils of length N.  Every thread owns EPT =
+// NPEN * N / NT elements, held in registers, and the transform is a Stockham
+// autosort sequence of radix-R stages: a stage runs unrolled radix-R DFTs on
+// the thread's registers, and the data cross between threads only between
+// stages, through one LDS buffer.  So a two-stage size (N = 64 .. 256) costs a
+// single LDS round trip, and the caller loads the first stage's inputs
+// straight from HBM and stores the last stage's outputs straight back.
+//
+// Thread layout.  In a stage of radix R with BPP = N / R butterflies per
+// pencil, the thread's slot i (i < EPT / R) is butterfly bf = tid + i * NT,
+// mapped to (pencil, q) either pencil-fastest (pen = bf % NPEN, q = bf / NPEN:
+// neighbouring lanes work on neighbouring pencils, for pencils strided in
+// memory) or q-fastest (pen = bf / BPP, q = bf % BPP: for contiguous pencils).
+// Slot i holds elements v[i*R + r], r < R, at pencil positions q + r * BPP on
+// input of the first stage, and at q + r * (N / R) on output of the last
+// stage.  The first stage of the reversed radix order has the same layout as
+// the last stage of the normal order, so a forward transform in one order and
+// an inverse in the other meet in registers.
 //
 // The transform is unnormalised: forward X_k = sum_n x_n exp(-2 pi i n k / N),
-// inverse x_n = sum_k X_k exp(+2 pi i n k / N).  Inter-stage twiddles come
-// from a table tw[j] = exp(-2 pi i j / N) computed in FP64 on the host and
-// rounded once to the working precision.
+// inverse with exp(+2 pi i n k / N).  Inter-stage twiddles come from a table
+// tw[j] = exp(-2 pi i j / N) computed in FP64 on the host, rounded once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,7 +44,7 @@ __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
   return cx<R>{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-// cos and sin of 2 pi m / 16, m = 0..7, to double precision.
+// cos and sin of 2 pi m / 16, m = 0..7.
 __device__ constexpr double kCos16[8] = {1.0,
                                          0.92387953251128675613,
                                          0.70710678118654752440,
@@ -71,11 +81,10 @@ __host__ __device__ constexpr int bitrev(int i, int bits) {
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// In-register DFT of size RAD (2..16), natural order in and out.
-// Decimation in frequency with radix-2 butterflies, then a bit-reversal
-// permutation; every index is a compile-time constant after unrolling.
+// In-register DFT of size RAD (2..16) on v[0 .. RAD), natural order in and
+// out: radix-2 decimation in frequency, then a bit-reversal permutation.
 template <typename R, int RAD, bool INV>
-__device__ __forceinline__ void dft(cx<R> (&v)[RAD]) {
+__device__ __forceinline__ void dft(cx<R>* v) {
 #pragma unroll
   for (int len = RAD; len >= 2; len >>= 1) {
     const int half = len / 2;
@@ -97,69 +106,134 @@ __device__ __forceinline__ void dft(cx<R> (&v)[RAD]) {
   for (int i = 0; i < RAD; ++i) v[i] = t[i];
 }
 
-// One Stockham stage of radix RAD after NS points have been combined.
-template <typename R, int N, int RAD, int NS, int NPEN, int PSTR, int NT, bool INV>
-__device__ __forceinline__ void stockham_stage(cx<R>* buf, const cx<R>* tw) {
-  constexpr int BPP = N / RAD;             // butterflies per pencil
-  constexpr int TOTAL = NPEN * BPP;
-  constexpr int BPT = (TOTAL + NT - 1) / NT;
-  cx<R> v[BPT][RAD];
+// Radix schedule per size (normal order); the reversed order runs it backwards.
+template <int N>
+struct Radices;
+template <> struct Radices<8> { static constexpr int n = 1; static constexpr int r[3] = {8, 1, 1}; };
+template <> struct Radices<16> { static constexpr int n = 1; static constexpr int r[3] = {16, 1, 1}; };
+template <> struct Radices<32> { static constexpr int n = 2; static constexpr int r[3] = {8, 4, 1}; };
+template <> struct Radices<64> { static constexpr int n = 2; static constexpr int r[3] = {8, 8, 1}; };
+template <> struct Radices<128> { static constexpr int n = 2; static constexpr int r[3] = {16, 8, 1}; };
+template <> struct Radices<256> { static constexpr int n = 2; static constexpr int r[3] = {16, 16, 1}; };
+template <> struct Radices<512> { static constexpr int n = 3; static constexpr int r[3] = {8, 8, 8}; };
+
+template <int N, bool REV>
+__host__ __device__ constexpr int radix_at(int s) {
+  return REV ? Radices<N>::r[Radices<N>::n - 1 - s] : Radices<N>::r[s];
+}
+
+template <int N, bool REV>
+__host__ __device__ constexpr int span_before(int s) {   // NS of stage s
+  int ns = 1;
+  for (int t = 0; t < s; ++t) ns *= radix_at<N, REV>(t);
+  return ns;
+}
+
+// Geometry of a tile: NPEN pencils, NT threads, pencil-fastest or q-fastest
+// thread mapping, LDS pencil stride PSTR and intra-pencil padding of one
+// element every 2^PADS elements (PADS = 0: none).
+template <int N, int NPEN, int NT, bool PENFAST, int PSTR, int PADS>
+struct Tile {
+  static constexpr int EPT = NPEN * N / NT;
+  __host__ __device__ static constexpr void split(int bf, int bpp, int& pen, int& q) {
+    if (PENFAST) {
+      pen = bf % NPEN;
+      q = bf / NPEN;
+    } else {
+      pen = bf / bpp;
+      q = bf % bpp;
+    }
+  }
+  __host__ __device__ static constexpr int lidx(int pen, int i) {
+    return pen * PSTR + (PADS ? i + (i >> PADS) : i);
+  }
+  // Pencil and position of the thread's element e on input of the first stage.
+  template <bool REV>
+  __host__ __device__ static constexpr void in_pos(int tid, int e, int& pen, int& pos) {
+    constexpr int R0 = radix_at<N, REV>(0);
+    int q = 0;
+    split(tid + (e / R0) * NT, N / R0, pen, q);
+    pos = q + (e % R0) * (N / R0);
+  }
+  // Pencil and position of the thread's element e on output of the last stage.
+  template <bool REV>
+  __host__ __device__ static constexpr void out_pos(int tid, int e, int& pen, int& pos) {
+    constexpr int RL = radix_at<N, REV>(Radices<N>::n - 1);
+    int q = 0;
+    split(tid + (e / RL) * NT, N / RL, pen, q);
+    pos = q + (e % RL) * (N / RL);
+  }
+};
+
+// Stage s of the (REV-ordered) schedule on registers: optional LDS read with
+// twiddles, DFTs, optional LDS write of the outputs.
+template <typename R, int N, class TL, int NT, bool INV, bool REV, int S>
+__device__ __forceinline__ void fft_stage(cx<R>* v, cx<R>* lds, const cx<R>* tw, bool read,
+                                          bool write) {
+  constexpr int RAD = radix_at<N, REV>(S);
+  constexpr int NS = span_before<N, REV>(S);
+  constexpr int BPP = N / RAD;
+  constexpr int SLOTS = TL::EPT / RAD;
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const int bf = tid + i * NT;
-    if (TOTAL % NT == 0 || bf < TOTAL) {
-      const int pen = bf / BPP, q = bf % BPP;
-      const cx<R>* base = buf + pen * PSTR;
+  for (int i = 0; i < SLOTS; ++i) {
+    int pen = 0, q = 0;
+    TL::split(tid + i * NT, BPP, pen, q);
+    cx<R>* x = v + i * RAD;
+    if (read) {
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[i][r] = base[q + r * BPP];
+      for (int r = 0; r < RAD; ++r) x[r] = lds[TL::lidx(pen, q + r * BPP)];
       if (NS > 1) {
         const int k = q % NS;
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
           const cx<R> w = tw[r * k * (N / (NS * RAD))];
-          v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+          x[r] = INV ? cmulc(x[r], w) : cmul(x[r], w);
         }
       }
-      dft<R, RAD, INV>(v[i]);
+    }
+    dft<R, RAD, INV>(x);
+  }
+  if (write) {
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) {
+      int pen = 0, q = 0;
+      TL::split(tid + i * NT, BPP, pen, q);
+      const int base = (q / NS) * NS * RAD + q % NS;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds[TL::lidx(pen, base + r * NS)] = v[i * RAD + r];
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const int bf = tid + i * NT;
-    if (TOTAL % NT == 0 || bf < TOTAL) {
-      const int pen = bf / BPP, q = bf % BPP;
-      const int k = q % NS;
-      cx<R>* base = buf + pen * PSTR + (q / NS) * NS * RAD + k;
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) base[r * NS] = v[i][r];
-    }
-  }
-  __syncthreads();
 }
 
-// Radix schedule per size.
-template <int N>
-struct Radices;
-template <> struct Radices<8> { static constexpr int n = 1, r0 = 8, r1 = 1, r2 = 1; };
-template <> struct Radices<16> { static constexpr int n = 1, r0 = 16, r1 = 1, r2 = 1; };
-template <> struct Radices<32> { static constexpr int n = 2, r0 = 8, r1 = 4, r2 = 1; };
-template <> struct Radices<64> { static constexpr int n = 2, r0 = 8, r1 = 8, r2 = 1; };
-template <> struct Radices<128> { static constexpr int n = 2, r0 = 16, r1 = 8, r2 = 1; };
-template <> struct Radices<256> { static constexpr int n = 2, r0 = 16, r1 = 16, r2 = 1; };
-template <> struct Radices<512> { static constexpr int n = 3, r0 = 8, r1 = 8, r2 = 8; };
-
-// Transform NPEN pencils of length N held in LDS.  The caller must have
-// synchronised after writing the tile; the tile is complete and visible to
-// the whole workgroup on return.
-template <typename R, int N, int NPEN, int PSTR, int NT, bool INV>
-__device__ __forceinline__ void lds_fft(cx<R>* buf, const cx<R>* tw) {
-  using P = Radices<N>;
-  stockham_stage<R, N, P::r0, 1, NPEN, PSTR, NT, INV>(buf, tw);
-  if constexpr (P::n >= 2) stockham_stage<R, N, P::r1, P::r0, NPEN, PSTR, NT, INV>(buf, tw);
-  if constexpr (P::n >= 3)
-    stockham_stage<R, N, P::r2, P::r0 * P::r1, NPEN, PSTR, NT, INV>(buf, tw);
+// Full transform of the thread's EPT registers (first-stage input layout in,
+// last-stage output layout out).  The LDS buffer must be free on entry (the
+// caller synchronises after its own last use); on return the LDS buffer may
+// still be read by other threads, so a caller reusing it synchronises first.
+template <typename R, int N, class TL, int NT, bool INV, bool REV>
+__device__ __forceinline__ void fft_regs(cx<R>* v, cx<R>* lds, const cx<R>* tw) {
+  constexpr int S = Radices<N>::n;
+  fft_stage<R, N, TL, NT, INV, REV, 0>(v, lds, tw, false, S > 1);
+  if constexpr (S > 1) {
+    __syncthreads();
+    fft_stage<R, N, TL, NT, INV, REV, 1>(v, lds, tw, true, false);
+  }
+  if constexpr (S > 2) {
+    __syncthreads();   // every stage-1 read is done before the buffer is rewritten
+    constexpr int RAD = radix_at<N, REV>(1);
+    constexpr int NS = span_before<N, REV>(1);
+    constexpr int BPP = N / RAD;
+#pragma unroll
+    for (int i = 0; i < TL::EPT / RAD; ++i) {
+      int pen = 0, q = 0;
+      TL::split(threadIdx.x + i * NT, BPP, pen, q);
+      const int base = (q / NS) * NS * RAD + q % NS;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds[TL::lidx(pen, base + r * NS)] = v[i * RAD + r];
+    }
+    __syncthreads();
+    fft_stage<R, N, TL, NT, INV, REV, 2>(v, lds, tw, true, false);
+  }
 }
 
 }  // namespace mf

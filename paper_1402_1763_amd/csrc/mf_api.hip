@@ -68,7 +68,7 @@ Shape shape_of(int n) {
 }
 
 struct Layout {
-  size_t tw, qthr, counts, tau, pk, table, status, partials, alpha, beta, spec, staging, total;
+  size_t tw, qthr, counts, tau, pk, table, status, partials, coef, spec, staging, total;
   size_t spec_elems, spec_stride;
   int n_wg_x;
 };
@@ -96,8 +96,7 @@ Layout make_layout(const mf_chain_desc& d) {
   L.table = take(nc * nb * 2 * rs);
   L.status = take(nc * 4);
   L.partials = take(nc * static_cast<size_t>(L.n_wg_x) * nb * 8);
-  L.alpha = take(nc * m * rs);
-  L.beta = take(nc * m * rs);
+  L.coef = take(nc * 2 * m * rs);
   L.spec = take(nc * L.spec_stride * 2 * rs);
   L.staging = take(m * rs);
   L.total = off;
@@ -189,8 +188,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   mf::SweepArgs<R> a{};
   char* ws = p->ws;
   a.spec = reinterpret_cast<mf::cx<R>*>(ws + p->L.spec);
-  a.alpha = reinterpret_cast<const R*>(ws + p->L.alpha);
-  a.beta = reinterpret_cast<const R*>(ws + p->L.beta);
+  a.coef = reinterpret_cast<const R*>(ws + p->L.coef);
   a.staging = reinterpret_cast<R*>(ws + p->L.staging);
   a.tau = reinterpret_cast<const double*>(ws + p->L.tau);
   a.pk = reinterpret_cast<double*>(ws + p->L.pk);
@@ -314,6 +312,46 @@ mf_status download_real(mf_problem* p, double* dst, const void* src, size_t coun
   return MF_OK;
 }
 
+template <typename R, int N>
+void permute_coef(std::vector<R>& out, const double* data, const double* noise_var, double tau) {
+  using T = mf::ZTile<R, N>;
+  const int tiles = N * (N / T::P);
+  out.assign(static_cast<size_t>(2) * N * N * N, R(0));
+  auto alpha = [&](size_t i) { return std::isinf(noise_var[i]) ? 1.0 : 1.0 - tau / noise_var[i]; };
+  auto beta = [&](size_t i) { return std::isinf(noise_var[i]) ? 0.0 : tau * data[i] / noise_var[i]; };
+  for (int tile = 0; tile < tiles; ++tile)
+    for (int e = 0; e < T::EPT; ++e)
+      for (int tid = 0; tid < T::NT; ++tid) {
+        int ix = 0, iya = 0, n = 0;
+        mf::zpass_coef_voxel<R, N>(tile, e, tid, ix, iya, n);
+        const size_t va = (static_cast<size_t>(ix) * N + iya) * N + n, vb = va + N;
+        R* o = &out[((static_cast<size_t>(tile) * T::EPT + e) * T::NT + tid) * 4];
+        o[0] = static_cast<R>(alpha(va));
+        o[1] = static_cast<R>(alpha(vb));
+        o[2] = static_cast<R>(beta(va));
+        o[3] = static_cast<R>(beta(vb));
+      }
+}
+
+template <typename R>
+mf_status upload_coef(mf_problem* p, int c, const double* data, const double* noise_var,
+                      double tau, hipStream_t st) {
+  std::vector<R> buf;
+  switch (p->desc.n) {
+    case 8: permute_coef<R, 8>(buf, data, noise_var, tau); break;
+    case 16: permute_coef<R, 16>(buf, data, noise_var, tau); break;
+    case 32: permute_coef<R, 32>(buf, data, noise_var, tau); break;
+    case 64: permute_coef<R, 64>(buf, data, noise_var, tau); break;
+    case 128: permute_coef<R, 128>(buf, data, noise_var, tau); break;
+    case 256: permute_coef<R, 256>(buf, data, noise_var, tau); break;
+    case 512: permute_coef<R, 512>(buf, data, noise_var, tau); break;
+  }
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.coef + static_cast<size_t>(c) * buf.size() * sizeof(R),
+                        buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st));
+  MF_HIP(hipStreamSynchronize(st));
+  return MF_OK;
+}
+
 mf_status set_state(mf_problem* p, int chain, const double* s, const double* pk, hipStream_t st) {
   const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
   const size_t rs = p->fp64() ? 8 : 4;
@@ -432,24 +470,15 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
       hipMemsetAsync(p->ws + L.partials, 0, static_cast<size_t>(nch) * L.n_wg_x * nb * 8, hs) != hipSuccess ||
       hipStreamSynchronize(hs) != hipSuccess)
     return cleanup(fail(MF_E_DEVICE, "uploading tables failed"));
-  // messenger coefficients in FP64: alpha = 1 - tau/N, beta = tau d / N
-  const size_t rs = p->fp64() ? 8 : 4;
-  std::vector<double> coef(m);
+  // messenger coefficients in FP64 (alpha = 1 - tau/N, beta = tau d / N),
+  // rounded once and stored in the z-pass thread order
   for (int c = 0; c < nch; ++c) {
-    for (size_t i = 0; i < m; ++i) {
-      const double nv = noise_var[c][i];
-      coef[i] = (std::isinf(nv)) ? 1.0 : 1.0 - tau[c] / nv;
-    }
-    if ((st = upload_real(p, p->ws + L.alpha + c * m * rs, coef.data(), m, hs)) != MF_OK)
-      return cleanup(st);
-    for (size_t i = 0; i < m; ++i) {
-      const double nv = noise_var[c][i];
-      coef[i] = (std::isinf(nv)) ? 0.0 : tau[c] * data[c][i] / nv;
-    }
-    if ((st = upload_real(p, p->ws + L.beta + c * m * rs, coef.data(), m, hs)) != MF_OK)
-      return cleanup(st);
+    st = p->fp64() ? upload_coef<double>(p, c, data[c], noise_var[c], tau[c], hs)
+                   : upload_coef<float>(p, c, data[c], noise_var[c], tau[c], hs);
+    if (st != MF_OK) return cleanup(st);
   }
   // initial state
+  const size_t rs = p->fp64() ? 8 : 4;
   if (hipMemsetAsync(p->ws + L.spec, 0, static_cast<size_t>(nch) * L.spec_stride * 2 * rs, hs) !=
       hipSuccess)
     return cleanup(fail(MF_E_DEVICE, "clearing the spectrum failed"));

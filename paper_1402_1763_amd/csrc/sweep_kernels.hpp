@@ -1,7 +1,7 @@
 // Kernels of one Gibbs sweep of the messenger-field sampler (gfx950).
 //
 // Device layout of a chain (R = float or double):
-//   alpha, beta  [ix][iy][iz]  R      messenger coefficients (see z-pass)
+//   coef         z-pass order  R      messenger coefficients (alpha, beta)
 //   spec         [kz][ix][iy]  cx<R>  half-complex working field, kz <= N/2
 //   table        [b][2]        R      per-bin (A_b, B_b) of the signal draw
 //   pk           [b]           double P_b in grid units (variance per voxel)
@@ -31,8 +31,7 @@ namespace mf {
 template <typename R>
 struct SweepArgs {
   cx<R>* spec;            // chain c at spec + c * spec_stride
-  const R* alpha;         // chain c at alpha + c * m
-  const R* beta;
+  const R* coef;          // chain c at coef + c * 2 m (z-pass thread order)
   R* staging;             // M reals, shared by all chains (state in/out)
   const double* tau;      // [chain]
   double* pk;             // [chain][nb]
@@ -56,33 +55,39 @@ struct SweepArgs {
 enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2 };
 
 // ---------------------------------------------------------------- tiles
+// z-pass: one ix, P consecutive iy (NPAIR complex pencils), pencil-fastest.
 template <typename R, int N>
 struct ZTile {
-  static constexpr int EPT = 16;                                   // elements / thread
-  static constexpr int P = N >= 32 ? (sizeof(R) == 4 ? 32 : 16) : N;  // z pencils / wg
-  static constexpr int NPAIR = P / 2;                              // complex pencils
-  static constexpr int PSTR = N + 1;
+  static constexpr int EPT = 16;
+  static constexpr int P = N >= 32 ? (sizeof(R) == 4 ? 32 : 16) : N;
+  static constexpr int NPAIR = P / 2;
   static constexpr int NT = NPAIR * N / EPT;
+  static constexpr int PSTR = N + 1;
+  using TL = Tile<N, NPAIR, NT, true, PSTR, 0>;
 };
 
+// y-pass: NPEN consecutive contiguous pencils, q-fastest, padded LDS.
 template <typename R, int N>
 struct YTile {
   static constexpr int EPT = 16;
-  static constexpr int CAP = sizeof(R) == 4 ? 4096 : 2048;          // elements / wg
-  static constexpr int NPEN = CAP / N < 1 ? 1 : (CAP / N > N ? N : CAP / N);
-  static constexpr int PSTR = N + 1;
+  static constexpr int CAP = sizeof(R) == 4 ? 4096 : 2048;
+  static constexpr int NPEN = CAP / N > N ? N : CAP / N;
   static constexpr int NT = NPEN * N / EPT;
+  static constexpr int PADS = ilog2(Radices<N>::r[0]);
+  static constexpr int PSTR = N + (N >> PADS);
+  using TL = Tile<N, NPEN, NT, false, PSTR, PADS>;
 };
 
+// x-pass: one kz plane, P consecutive iy columns, pencil-fastest.
 template <typename R, int N>
 struct XTile {
   static constexpr int EPT = 16;
   static constexpr int CAP = sizeof(R) == 4 ? 8192 : 4096;
-  static constexpr int P = CAP / N > N ? N : CAP / N;              // x pencils (columns)
-  static constexpr int PSTR = N + 1;
+  static constexpr int P = CAP / N > N ? N : CAP / N;
   static constexpr int NT = P * N / EPT;
-  static constexpr int K = N < 16 ? N : 16;                         // rows per chunk
+  static constexpr int PSTR = N + 1;
   static constexpr int NWAVES = (NT + 63) / 64;
+  using TL = Tile<N, P, NT, true, PSTR, 0>;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -109,7 +114,6 @@ __device__ __forceinline__ void st2(cx<double>* p, cx<double> a, cx<double> b) {
   reinterpret_cast<double2*>(p)[0] = make_double2(a.x, a.y);
   reinterpret_cast<double2*>(p)[1] = make_double2(b.x, b.y);
 }
-
 __device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
   const float4 t = *reinterpret_cast<const float4*>(p);
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
@@ -119,120 +123,146 @@ __device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
   const double2 t1 = reinterpret_cast<const double2*>(p)[1];
   v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
 }
-__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-__device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
-  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
-  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
-}
-
-// Four unit normals of the messenger draw of voxels (ix, iy, 4g .. 4g+3).
-template <typename R>
-__device__ __forceinline__ void messenger_normals(uint32_t w0, const SweepArgs<R>& a,
-                                                  uint32_t chain, R (&g)[4]) {
-  const Words4 w = philox4x32_10(w0, a.sweep, kPhaseMessenger, chain, a.key0, a.key1);
-  box_muller(w.x0, w.x1, g[0], g[1]);
-  box_muller(w.x2, w.x3, g[2], g[3]);
-}
 
 // ---------------------------------------------------------------- z-pass
-// Workgroup = one ix and P consecutive iy; the z pencils are processed in
-// pairs (a, b) = (iy, iy + 1) packed as one complex pencil a + i b.
-//   load   : spec[kz][ix][iy..] half spectra A, B -> Z[k] = A_k + i B_k, k < N,
-//            with A_{N-k} = conj(A_k) (imaginary parts of kz = 0, N/2 dropped)
-//   c2r    : z = inverse DFT(Z); s_a = Re z, s_b = Im z
-//   draw   : t = alpha s + beta + sqrt(tau alpha) G   (messenger conditional)
-//   r2c    : W = DFT(t_a + i t_b); A'_k = (W_k + conj W_{N-k}) / 2,
-//            B'_k = (W_k - conj W_{N-k}) / (2i), k <= N/2 -> spec
-// alpha = 1 - tau/N_i, beta = tau d_i / N_i on observed voxels and (1, 0) on
-// unobserved ones, i.e. mean tau/N d + (N - tau)/N s and variance
-// tau (N - tau)/N, the messenger conditional with T = tau, R in {0, 1}.
+// Messenger coefficients are stored in the z-pass's thread order so that each
+// lane's loads are contiguous: entry ((tile * EPT + e) * NT + tid) holds
+// (alpha_a, alpha_b, beta_a, beta_b) of the voxels (ix, iy0 + 2p (+1), n)
+// that thread tid holds as element e after the inverse z-DFT, where
+// tile = ix * (N / P) + iy0 / P.  alpha = 1 - tau/N_i, beta = tau d_i / N_i
+// on observed voxels and (1, 0) elsewhere.
+template <typename R, int N>
+__host__ __device__ inline void zpass_coef_voxel(int tile, int e, int tid, int& ix, int& iya,
+                                                 int& n) {
+  using T = ZTile<R, N>;
+  int p = 0;
+  T::TL::template out_pos<false>(tid, e, p, n);
+  ix = tile / (N / T::P);
+  iya = (tile % (N / T::P)) * T::P + 2 * p;
+}
+
+// Workgroup = one ix and P consecutive iy; z pencils (iy, iy + 1) are packed
+// as one complex pencil a + i b.
+//   load    : Z_k = A_k + i B_k from the half spectra, Hermitian-extended
+//             (A_{N-k} = conj A_k; imaginary parts of kz = 0, N/2 dropped),
+//             straight into the registers of the first inverse stage
+//   c2r     : z = inverse DFT(Z); s_a = Re z, s_b = Im z
+//   draw    : t = alpha s + beta + sqrt(tau alpha) G  -- the messenger
+//             conditional with T = tau, R in {0, 1}: mean tau/N d +
+//             (N - tau)/N s, variance tau (N - tau)/N (s and 1/N-free t on
+//             unobserved voxels)
+//   r2c     : W = DFT(t_a + i t_b), A'_k = (W_k + conj W_{N-k}) / 2,
+//             B'_k = (W_k - conj W_{N-k}) / (2i), k <= N/2 -> spec
+// The unit normals of voxel (ix, iy, n) come from Philox counter
+// ((ix N + iy) N/4 + n mod N/4, sweep, 0, chain), normal n div (N/4) of the
+// call; a thread's elements n = q + (N/R_L) r cover all four normals of a call.
 template <typename R, int N, int MODE>
 __global__ void __launch_bounds__((ZTile<R, N>::NT))
 zpass_kernel(SweepArgs<R> a) {
   using T = ZTile<R, N>;
-  constexpr int NPAIR = T::NPAIR, PSTR = T::PSTR, NT = T::NT, H = N / 2;
-  __shared__ cx<R> lds[NPAIR * PSTR];
+  using TL = typename T::TL;
+  constexpr int NPAIR = T::NPAIR, NT = T::NT, EPT = T::EPT, H = N / 2;
+  constexpr int RL = radix_at<N, false>(Radices<N>::n - 1);
+  constexpr int NSL = N / RL;
+  __shared__ cx<R> lds[NPAIR * T::PSTR];
   __shared__ cx<R> tw[N];
   const int tid = threadIdx.x;
-  const int iy0 = blockIdx.x * T::P;
+  const int blk = blockIdx.x;
+  const int iy0 = blk * T::P;
   const int ix = blockIdx.y;
   const int c = (MODE == kZSweep) ? static_cast<int>(blockIdx.z) : a.staging_chain;
   cx<R>* spec = a.spec + static_cast<size_t>(c) * a.spec_stride;
   load_twiddles(tw, a.tw, N, NT);
+  cx<R> v[EPT];
 
   if (MODE != kZSetState) {
-    for (int it = tid; it < (H + 1) * NPAIR; it += NT) {
-      const int k = it / NPAIR, p = it % NPAIR;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int p = 0, k = 0;
+      TL::template in_pos<false>(tid, e, p, k);
+      const int kk = k <= H ? k : N - k;
       cx<R> A, B;
-      ld2(spec + (static_cast<size_t>(k) * N + ix) * N + iy0 + 2 * p, A, B);
-      cx<R>* z = lds + p * PSTR;
-      if (k == 0 || k == H) {
-        z[k] = cx<R>{A.x, B.x};
-      } else {
-        z[k] = cx<R>{A.x - B.y, A.y + B.x};
-        z[N - k] = cx<R>{A.x + B.y, B.x - A.y};
-      }
+      ld2(spec + (static_cast<size_t>(kk) * N + ix) * N + iy0 + 2 * p, A, B);
+      if (k == 0 || k == H) v[e] = cx<R>{A.x, B.x};
+      else if (k < H) v[e] = cx<R>{A.x - B.y, A.y + B.x};
+      else v[e] = cx<R>{A.x + B.y, B.x - A.y};
     }
-    __syncthreads();
-    lds_fft<R, N, NPAIR, PSTR, NT, true>(lds, tw);
+    fft_regs<R, N, TL, NT, true, false>(v, lds, tw);
+    if (MODE == kZGetState) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        int p = 0, n = 0;
+        TL::template out_pos<false>(tid, e, p, n);
+        const size_t ra = (static_cast<size_t>(ix) * N + iy0 + 2 * p) * N + n;
+        a.staging[ra] = v[e].x;
+        a.staging[ra + N] = v[e].y;
+      }
+      return;
+    }
+  }
+
+  if (MODE == kZSetState) {
+    // the stored z transform carries the 1/N of the inverse z-DFT
+    constexpr R inv_n = R(1) / R(N);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int p = 0, n = 0;
+      TL::template out_pos<false>(tid, e, p, n);
+      const size_t ra = (static_cast<size_t>(ix) * N + iy0 + 2 * p) * N + n;
+      v[e] = cx<R>{a.staging[ra] * inv_n, a.staging[ra + N] * inv_n};
+    }
   } else {
-    __syncthreads();
-  }
-
-  const R tau = static_cast<R>(a.tau[c]);
-  const size_t chain_off = static_cast<size_t>(c) * a.m;
-  for (int it = tid; it < NPAIR * (N / 4); it += NT) {
-    const int g = it % (N / 4), p = it / (N / 4);
-    const int iya = iy0 + 2 * p;
-    const size_t ra = (static_cast<size_t>(ix) * N + iya) * N + 4 * g;
-    cx<R>* z = lds + p * PSTR + 4 * g;
-    if (MODE == kZSetState) {
-      // the stored z transform carries the 1/N of the inverse z-DFT
-      R sa[4], sb[4];
-      ld4(a.staging + ra, sa);
-      ld4(a.staging + ra + N, sb);
-      constexpr R inv_n = R(1) / R(N);
+    const R tau = static_cast<R>(a.tau[c]);
+    const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m +
+                    static_cast<size_t>(ix * (N / T::P) + blk) * EPT * NT * 4;
+    const uint32_t chain = a.chain0 + c;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) z[l] = cx<R>{sa[l] * inv_n, sb[l] * inv_n};
-    } else if (MODE == kZGetState) {
-      R sa[4], sb[4];
+    for (int i = 0; i < EPT / RL; ++i) {
+      int p = 0, q = 0;
+      TL::split(tid + i * NT, NSL, p, q);
+      const uint32_t wa = static_cast<uint32_t>((ix * N + iy0 + 2 * p) * (N / 4) + q);
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        sa[l] = z[l].x;
-        sb[l] = z[l].y;
-      }
-      st4(a.staging + ra, sa);
-      st4(a.staging + ra + N, sb);
-    } else {
-      R al[4], bl[4], ab[4], bb[4], ga[4], gb[4];
-      ld4(a.alpha + chain_off + ra, al);
-      ld4(a.beta + chain_off + ra, bl);
-      ld4(a.alpha + chain_off + ra + N, ab);
-      ld4(a.beta + chain_off + ra + N, bb);
-      const uint32_t chain = a.chain0 + c;
-      const uint32_t w0 = static_cast<uint32_t>((ix * N + iya) * (N / 4) + g);
-      messenger_normals(w0, a, chain, ga);
-      messenger_normals(w0 + N / 4, a, chain, gb);
+      for (int cq = 0; cq < RL / 4; ++cq) {
+        R ga[4], gb[4];
+        {
+          const Words4 w = philox4x32_10(wa + NSL * cq, a.sweep, kPhaseMessenger, chain,
+                                         a.key0, a.key1);
+          box_muller(w.x0, w.x1, ga[0], ga[1]);
+          box_muller(w.x2, w.x3, ga[2], ga[3]);
+        }
+        {
+          const Words4 w = philox4x32_10(wa + N / 4 + NSL * cq, a.sweep, kPhaseMessenger,
+                                         chain, a.key0, a.key1);
+          box_muller(w.x0, w.x1, gb[0], gb[1]);
+          box_muller(w.x2, w.x3, gb[2], gb[3]);
+        }
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const cx<R> s = z[l];
-        const R ta = al[l] * s.x + bl[l] + sqrt(tau * al[l]) * ga[l];
-        const R tb = ab[l] * s.y + bb[l] + sqrt(tau * ab[l]) * gb[l];
-        z[l] = cx<R>{ta, tb};
+        for (int j = 0; j < 4; ++j) {
+          const int e = i * RL + cq + j * (RL / 4);
+          R cf[4];
+          ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
+          const cx<R> s = v[e];
+          const R ta = cf[0] * s.x + cf[2] + sqrt(tau * cf[0]) * ga[j];
+          const R tb = cf[1] * s.y + cf[3] + sqrt(tau * cf[1]) * gb[j];
+          v[e] = cx<R>{ta, tb};
+        }
       }
     }
   }
-  if (MODE == kZGetState) return;
+  __syncthreads();   // every lane is done with the inverse transform's LDS reads
+  fft_regs<R, N, TL, NT, false, true>(v, lds, tw);
   __syncthreads();
-  lds_fft<R, N, NPAIR, PSTR, NT, false>(lds, tw);
-
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    int p = 0, k = 0;
+    TL::template out_pos<true>(tid, e, p, k);
+    lds[TL::lidx(p, k)] = v[e];
+  }
+  __syncthreads();
   for (int it = tid; it < (H + 1) * NPAIR; it += NT) {
     const int k = it / NPAIR, p = it % NPAIR;
-    const cx<R>* z = lds + p * PSTR;
-    const cx<R> u = z[k];
-    const cx<R> w = z[(N - k) & (N - 1)];
+    const cx<R> u = lds[TL::lidx(p, k)];
+    const cx<R> w = lds[TL::lidx(p, (N - k) & (N - 1))];
     const cx<R> A{R(0.5) * (u.x + w.x), R(0.5) * (u.y - w.y)};
     const cx<R> B{R(0.5) * (u.y + w.y), R(0.5) * (w.x - u.x)};
     st2(spec + (static_cast<size_t>(k) * N + ix) * N + iy0 + 2 * p, A, B);
@@ -245,25 +275,27 @@ template <typename R, int N, bool INV>
 __global__ void __launch_bounds__((YTile<R, N>::NT))
 ypass_kernel(SweepArgs<R> a) {
   using T = YTile<R, N>;
-  constexpr int NPEN = T::NPEN, PSTR = T::PSTR, NT = T::NT, E = NPEN * N;
-  __shared__ cx<R> lds[NPEN * PSTR];
+  using TL = typename T::TL;
+  constexpr int NT = T::NT, EPT = T::EPT;
+  __shared__ cx<R> lds[T::NPEN * T::PSTR];
   __shared__ cx<R> tw[N];
   const int tid = threadIdx.x;
   cx<R>* base = a.spec + static_cast<size_t>(blockIdx.z) * a.spec_stride +
-                static_cast<size_t>(blockIdx.x) * E;
+                static_cast<size_t>(blockIdx.x) * T::NPEN * N;
   load_twiddles(tw, a.tw, N, NT);
-  for (int it = tid; it < E / 2; it += NT) {
-    const int e = 2 * it, pen = e / N, n = e % N;
-    cx<R> u, v;
-    ld2(base + e, u, v);
-    lds[pen * PSTR + n] = u;
-    lds[pen * PSTR + n + 1] = v;
+  cx<R> v[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    int pen = 0, n = 0;
+    TL::template in_pos<false>(tid, e, pen, n);
+    v[e] = base[pen * N + n];
   }
-  __syncthreads();
-  lds_fft<R, N, NPEN, PSTR, NT, INV>(lds, tw);
-  for (int it = tid; it < E / 2; it += NT) {
-    const int e = 2 * it, pen = e / N, n = e % N;
-    st2(base + e, lds[pen * PSTR + n], lds[pen * PSTR + n + 1]);
+  fft_regs<R, N, TL, NT, INV, false>(v, lds, tw);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    int pen = 0, n = 0;
+    TL::template out_pos<false>(tid, e, pen, n);
+    base[pen * N + n] = v[e];
   }
 }
 
@@ -272,7 +304,7 @@ __device__ __forceinline__ int wavenumber(int i, int n) { return i <= n / 2 ? i 
 
 // Bin of q >= 1: the largest b with Q_b <= q (thresholds Q_b in LDS).
 __device__ __forceinline__ int bin_of(int q, const int32_t* qthr, int nb, float qscale) {
-  int b = static_cast<int>(sqrtf(static_cast<float>(q) * qscale));
+  int b = static_cast<int>(__builtin_amdgcn_sqrtf(static_cast<float>(q) * qscale));
   b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
   if (b + 1 < nb && q >= qthr[b + 1]) ++b;
   if (b > 0 && q < qthr[b]) --b;
@@ -280,24 +312,30 @@ __device__ __forceinline__ int bin_of(int q, const int32_t* qthr, int nb, float 
 }
 
 // Workgroup = one kz plane and P consecutive iy columns; x pencils are the
-// columns.  After the forward x-DFT the tile holds t^ for modes
-// (ix, iy, kz).  Each mode is drawn from the signal conditional
-//   s^ = f t^ + sqrt(v/2) (G_re + i G_im),  f = P/(P + tau), v = M tau f
-// (stored divided by M: s^/M = A_b t^ + B_b (G_re + i G_im) with
-// A_b = f/M, B_b = sqrt(tau f / (2M))).  Self-conjugate modes are real with
-// the full variance; on the kz = 0 and kz = N/2 planes the member of a
-// conjugate pair with the larger ix*N + iy uses its partner's draws
-// conjugated; q = 0 gives 0.  Shell sums of w |s^/M|^2 (w = 1 on kz = 0, N/2,
-// else 2) go to per-wave LDS histograms (a wave's atomics land in a fixed
-// order), then to one partial per workgroup.
+// columns.  After the forward x-DFT a thread holds t^ of modes (ix, iy, kz)
+// with ix = q + (N/R_L) r; each is drawn from the signal conditional
+//   s^ = f t^ + sqrt(v/2) (G_re + i G_im),  f = P/(P + tau), v = M tau f,
+// stored divided by M: s^/M = A_b t^ + B_b (G_re + i G_im), A_b = f/M,
+// B_b = sqrt(tau f / (2M)).  Self-conjugate modes are real with the full
+// variance; on the kz = 0 and kz = N/2 planes the member of a conjugate pair
+// with the larger ix*N + iy uses its partner's normals conjugated; q = 0
+// gives 0.  (G_re, G_im) of (ix, iy, kz) come from Philox counter
+// ((kz N + iy) N/2 + ix mod N/2, sweep, 1, chain): words (x0, x1) for
+// ix < N/2, (x2, x3) for ix >= N/2.  Shell sums of w |s^/M|^2 (w = 1 on
+// kz = 0, N/2, else 2) go to per-wave LDS histograms (a wave's atomics land in
+// a fixed order), then to one partial per workgroup.  The inverse x-DFT runs
+// in the reversed radix order so it starts from the same registers.
 template <typename R, int N>
 __global__ void __launch_bounds__((XTile<R, N>::NT))
 xpass_kernel(SweepArgs<R> a) {
   using T = XTile<R, N>;
-  constexpr int P = T::P, PSTR = T::PSTR, NT = T::NT, K = T::K, H = N / 2;
-  __shared__ cx<R> lds[P * PSTR];
+  using TL = typename T::TL;
+  constexpr int P = T::P, NT = T::NT, EPT = T::EPT, H = N / 2;
+  constexpr int RL = radix_at<N, false>(Radices<N>::n - 1);
+  constexpr int NSL = N / RL;
+  __shared__ cx<R> lds[P * T::PSTR];
   __shared__ cx<R> tw[N];
-  extern __shared__ double dyn[];      // hist[NWAVES][nb], then table (2 nb R), qthr
+  extern __shared__ double dyn[];      // hist[NWAVES][nb], table (2 nb R), qthr (nb)
   double* hist = dyn;
   R* tab = reinterpret_cast<R*>(hist + T::NWAVES * a.nb);
   int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * a.nb);
@@ -313,48 +351,50 @@ xpass_kernel(SweepArgs<R> a) {
   for (int i = tid; i < T::NWAVES * nb; i += NT) hist[i] = 0.0;
   for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
   for (int i = tid; i < nb; i += NT) qthr[i] = a.qthr[i];
-  for (int it = tid; it < N * P; it += NT) {
-    const int col = it % P, ix = it / P;
-    lds[col * PSTR + ix] = spec[static_cast<size_t>(ix) * N + iy0 + col];
+  cx<R> v[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    int col = 0, ix = 0;
+    TL::template in_pos<false>(tid, e, col, ix);
+    v[e] = spec[static_cast<size_t>(ix) * N + iy0 + col];
   }
-  __syncthreads();
-  lds_fft<R, N, P, PSTR, NT, false>(lds, tw);
+  __syncthreads();   // tables and histograms ready (single-stage sizes have no barrier)
+  fft_regs<R, N, TL, NT, false, false>(v, lds, tw);
 
   const bool herm = (kz == 0 || kz == H);
   const double wgt = herm ? 1.0 : 2.0;
   const float qscale = static_cast<float>(4.0 * nb * nb / (3.0 * N * N));
   const uint32_t chain = a.chain0 + c;
-  const int mz2 = kz * kz;
   double* my_hist = hist + (tid / 64) * nb;
-  for (int ci = tid; ci < P * (N / K); ci += NT) {
-    const int col = ci % P, row0 = (ci / P) * K;
+#pragma unroll
+  for (int i = 0; i < EPT / RL; ++i) {
+    int col = 0, q = 0;
+    TL::split(tid + i * NT, NSL, col, q);
     const int iy = iy0 + col;
     const int my = wavenumber(iy, N);
-    const int r2 = my * my + mz2;
-    cx<R>* colp = lds + col * PSTR;
-    int cur = -1;
-    double acc = 0.0;
-#pragma unroll 2
-    for (int ix = row0; ix < row0 + K; ix += 2) {
+    const int r2 = my * my + kz * kz;
+#pragma unroll
+    for (int r = 0; r < RL / 2; ++r) {
+      const int ixl = q + NSL * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
       R g[4];
       {
-        const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ix / 2);
+        const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
         const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, chain, a.key0, a.key1);
         box_muller(w.x0, w.x1, g[0], g[1]);
         box_muller(w.x2, w.x3, g[2], g[3]);
       }
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int x = ix + e;
+      for (int h = 0; h < 2; ++h) {
+        const int e = i * RL + r + h * (RL / 2);
+        const int x = ixl + h * H;
         const int mx = wavenumber(x, N);
-        const int q = mx * mx + r2;
+        const int qq = mx * mx + r2;
         cx<R> out{R(0), R(0)};
-        int b = -1;
-        if (q > 0) {
-          b = bin_of(q, qthr, nb, qscale);
+        if (qq > 0) {
+          const int b = bin_of(qq, qthr, nb, qscale);
           const R A = tab[2 * b], B = tab[2 * b + 1];
-          const cx<R> t = colp[x];
-          R gre = g[2 * e], gim = g[2 * e + 1];
+          const cx<R> t = v[e];
+          R gre = g[2 * h], gim = g[2 * h + 1];
           bool selfconj = false;
           if (herm) {
             const int px = (N - x) & (N - 1), py = (N - iy) & (N - 1);
@@ -362,41 +402,33 @@ xpass_kernel(SweepArgs<R> a) {
             if (plin == lin) {
               selfconj = true;
             } else if (plin < lin) {
-              const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + px / 2);
+              const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px & (H - 1)));
               const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, chain, a.key0, a.key1);
               R h0, h1;
-              if (px & 1) box_muller(w.x2, w.x3, h0, h1);
+              if (px >= H) box_muller(w.x2, w.x3, h0, h1);
               else box_muller(w.x0, w.x1, h0, h1);
               gre = h0;
               gim = -h1;
             }
           }
-          if (selfconj) {
-            out = cx<R>{A * t.x + R(1.4142135623730950488) * B * gre, R(0)};
-          } else {
-            out = cx<R>{A * t.x + B * gre, A * t.y + B * gim};
-          }
-        }
-        colp[x] = out;
-        if (b != cur) {
-          if (cur >= 0) atomicAdd(my_hist + cur, acc);
-          cur = b;
-          acc = 0.0;
-        }
-        if (b >= 0) {
+          if (selfconj) out = cx<R>{A * t.x + R(1.4142135623730950488) * B * gre, R(0)};
+          else out = cx<R>{A * t.x + B * gre, A * t.y + B * gim};
           const double ox = static_cast<double>(out.x), oy = static_cast<double>(out.y);
-          acc += wgt * (ox * ox + oy * oy);
+          atomicAdd(my_hist + b, wgt * (ox * ox + oy * oy));
         }
+        v[e] = out;
       }
     }
-    if (cur >= 0) atomicAdd(my_hist + cur, acc);
   }
-  __syncthreads();
-  lds_fft<R, N, P, PSTR, NT, true>(lds, tw);
-  for (int it = tid; it < N * P; it += NT) {
-    const int col = it % P, ix = it / P;
-    spec[static_cast<size_t>(ix) * N + iy0 + col] = lds[col * PSTR + ix];
+  __syncthreads();   // every lane is done with the forward transform's LDS reads
+  fft_regs<R, N, TL, NT, true, true>(v, lds, tw);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    int col = 0, ix = 0;
+    TL::template out_pos<true>(tid, e, col, ix);
+    spec[static_cast<size_t>(ix) * N + iy0 + col] = v[e];
   }
+  __syncthreads();   // all histogram atomics are done
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
   for (int b = tid; b < nb; b += NT) {
