@@ -41,15 +41,15 @@ def source_digest() -> str:
 def algorithmic_bytes(n: int, real_bytes: int, n_bins: int, n_wg_x: int) -> dict:
     """Bytes each sweep kernel must move: the half-complex field is read and
     written once per pass, the z-pass also reads the two messenger
-    coefficients per voxel; the P draw reads the shell partials."""
+    coefficients per voxel; the P draw (inside the inverse y-pass) reads the
+    shell partials."""
     m = n ** 3
     spec = (n // 2 + 1) * n * n * 2 * real_bytes
     return {
         "zpass": 2 * spec + 2 * m * real_bytes,
         "yfwd": 2 * spec,
         "xpass": 2 * spec + n_wg_x * n_bins * 8,
-        "pkdraw": n_wg_x * n_bins * 8 + n_bins * (16 + 2 * real_bytes),
-        "yinv": 2 * spec,
+        "yinv_pk": 2 * spec + n_wg_x * n_bins * 8 + n_bins * (16 + 2 * real_bytes),
     }
 
 
@@ -149,7 +149,7 @@ def main():
 
     real_bytes = 8 if w.precision == "fp64" else 4
     n = w.n
-    xp = {4: min(n, 8192 // n), 8: min(n, 4096 // n)}[real_bytes]
+    xp = min(n, 4096 // n)
     n_wg_x = (n // 2 + 1) * (n // xp)
     alg = algorithmic_bytes(n, real_bytes, w.n_bins, n_wg_x)
     sweep_bytes = sum(alg.values())

@@ -81,8 +81,8 @@ typedef struct mf_problem mf_problem;
 /* Number of sweep kernels reported by mf_gibbs_sweep_timed, in launch order:
  * 0 z-pass (inverse z-FFT, messenger draw, forward z-FFT), 1 forward y-FFT,
  * 2 x-pass (forward x-FFT, signal draw, shell sums, inverse x-FFT),
- * 3 P(k) draw, 4 inverse y-FFT. */
-#define MF_NUM_KERNELS 5
+ * 3 inverse y-FFT together with the P(k) draw. */
+#define MF_NUM_KERNELS 4
 
 /* Returns 1 if N is a supported grid side, else 0. */
 int32_t mf_supported_n(int32_t n);

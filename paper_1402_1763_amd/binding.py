@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmfgibbs.so")
+# MFGIBBS_LIB selects another build of the same library (e.g. tuned variants).
+LIB_PATH = os.environ.get("MFGIBBS_LIB") or os.path.join(HERE, "libmfgibbs.so")
 
 MF_OK = 0
 MF_E_INVALID_ARG = -1
@@ -26,8 +27,8 @@ MF_E_WORKSPACE = -6
 MF_E_STATE = -7
 MF_PREC_FP64 = 0
 MF_PREC_FP32 = 1
-MF_NUM_KERNELS = 5
-KERNEL_NAMES = ("zpass", "yfwd", "xpass", "pkdraw", "yinv")
+MF_NUM_KERNELS = 4
+KERNEL_NAMES = ("zpass", "yfwd", "xpass", "yinv_pk")
 
 # Symbols declared in include/mf.h, with their ctypes signatures.
 _c_double_p = ctypes.POINTER(ctypes.c_double)

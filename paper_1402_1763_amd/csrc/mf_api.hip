@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mf.h"
+#include "mf.h"
 #include "sweep_kernels.hpp"
 
 namespace {
@@ -211,7 +211,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   return a;
 }
 
-enum KernelId { kZ = 0, kYF = 1, kX = 2, kPk = 3, kYI = 4, kZSet = 10, kZGet = 11, kTable = 12 };
+enum KernelId { kZ = 0, kYF = 1, kX = 2, kYI = 3, kZSet = 10, kZGet = 11, kTable = 12 };
 
 template <typename R, int N>
 void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
@@ -220,6 +220,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
   using XT = mf::XTile<R, N>;
   const dim3 zgrid(N / ZT::P, N, nch), zgrid1(N / ZT::P, N, 1);
   const dim3 ygrid((N / 2 + 1) * N / YT::NPEN, 1, nch);
+  const dim3 yigrid((N / 2 + 1) * N / YT::NPEN + a.nb, 1, nch);
   const dim3 xgrid(N / XT::P, N / 2 + 1, nch);
   switch (id) {
     case kZ:
@@ -235,16 +236,13 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), ygrid, dim3(YT::NT), 0, st, a);
       break;
     case kYI:
-      hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>), ygrid, dim3(YT::NT), 0, st, a);
+      hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>), yigrid, dim3(YT::NT), 0, st, a);
       break;
     case kX: {
-      const size_t dyn = XT::NWAVES * a.nb * sizeof(double) + 2 * a.nb * sizeof(R) + a.nb * 4;
+      const size_t dyn = XT::NHIST * a.nb * sizeof(double) + 2 * a.nb * sizeof(R) + a.nb * 4;
       hipLaunchKernelGGL((mf::xpass_kernel<R, N>), xgrid, dim3(XT::NT), dyn, st, a);
       break;
     }
-    case kPk:
-      hipLaunchKernelGGL((mf::pk_draw_kernel<R>), dim3(a.nb, nch), dim3(mf::kPkThreads), 0, st, a);
-      break;
     case kTable:
       hipLaunchKernelGGL((mf::pk_table_kernel<R>), dim3((a.nb + 63) / 64, nch), dim3(64), 0, st, a);
       break;
@@ -283,7 +281,7 @@ mf_status launch_checked(mf_problem* p, int id, uint64_t sweep, int staging_chai
   return MF_OK;
 }
 
-const int kSweepOrder[MF_NUM_KERNELS] = {kZ, kYF, kX, kPk, kYI};
+const int kSweepOrder[MF_NUM_KERNELS] = {kZ, kYF, kX, kYI};
 
 // Host FP64 -> device R copy through a temporary host buffer.
 mf_status upload_real(mf_problem* p, void* dst, const double* src, size_t count, hipStream_t st) {

@@ -10,12 +10,12 @@
 // (a real-to-half-complex DFT of each z pencil), so keeping the state costs
 // no extra pass.
 //
-// One sweep = five launches:
+// One sweep = four launches:
 //   z-pass  : inverse z-DFT (-> s), messenger draw t, forward z-DFT of t
 //   y-pass  : forward y-DFT
 //   x-pass  : forward x-DFT (-> t^), signal draw s^, shell sums, inverse x-DFT
-//   pk-draw : per-bin reduction of the shell sums and inverse-gamma draw
-//   y-pass  : inverse y-DFT
+//   y-pass  : inverse y-DFT, plus the per-bin reduction of the shell sums and
+//             the inverse-gamma draw of P(k) in extra workgroups
 // The signal draw folds the inverse transform's 1/M into s^, so the stored
 // field is s^/M and every DFT is unnormalised.
 #pragma once
@@ -82,11 +82,13 @@ struct YTile {
 template <typename R, int N>
 struct XTile {
   static constexpr int EPT = 16;
-  static constexpr int CAP = sizeof(R) == 4 ? 8192 : 4096;
+  static constexpr int CAP = 4096;
   static constexpr int P = CAP / N > N ? N : CAP / N;
   static constexpr int NT = P * N / EPT;
   static constexpr int PSTR = N + 1;
   static constexpr int NWAVES = (NT + 63) / 64;
+  static constexpr int HG = 2;            // histogram copies per wave (by lane % HG)
+  static constexpr int NHIST = NWAVES * HG;
   using TL = Tile<N, P, NT, true, PSTR, 0>;
 };
 
@@ -269,8 +271,65 @@ zpass_kernel(SweepArgs<R> a) {
   }
 }
 
+// ---------------------------------------------------------------- P(k)
+// Per-bin table of the signal draw from P (grid units), in FP64.
+template <typename R>
+__device__ __forceinline__ void write_table(R* tab, int b, double p, double tau, double m) {
+  const double f = p / (p + tau);
+  tab[2 * b] = static_cast<R>(f / m);
+  tab[2 * b + 1] = static_cast<R>(sqrt(tau * f / (2.0 * m)));
+}
+
+// P(k) step of bin b of chain c by one workgroup of NTH threads (a power of
+// two): sums the x-pass partials in a fixed order (strided per thread, then a
+// tree in `red`, NTH doubles), forms sigma_b = M^2 sum w |s^/M|^2 and draws
+// P_b = sigma_b / (2 M g), g ~ Gamma(n_b / 2, 1) -- the inverse-gamma
+// conditional of P_b under Jeffreys' prior -- then refreshes (A_b, B_b).
+template <typename R, int NTH>
+__device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int c, double* red) {
+  const int tid = threadIdx.x;
+  const double* part = a.partials + (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x;
+  double s = 0.0;
+  for (int w = tid; w < a.n_wg_x; w += NTH) s += part[w];
+  red[tid] = s;
+  __syncthreads();
+  for (int h = NTH / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  const double m = static_cast<double>(a.m);
+  const double sigma = red[0] * m * m;
+  const double tau = a.tau[c];
+  double* pk = a.pk + static_cast<size_t>(c) * a.nb;
+  double p = pk[b];
+  if (a.sample_pk && a.counts[b] > 0.0) {
+    const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.sweep,
+                              a.chain0 + c, a.key0, a.key1);
+    p = sigma / (2.0 * m * g);
+    if (!(g > 0.0) || !isfinite(p) || !isfinite(sigma)) {
+      atomicOr(a.status + c, 1u);
+      p = pk[b];
+    }
+    pk[b] = p;
+  }
+  write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b, p, tau, m);
+}
+
+// Table from the current P of every chain (set-up and state restore).
+template <typename R>
+__global__ void pk_table_kernel(SweepArgs<R> a) {
+  const int c = blockIdx.y;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < a.nb; b += gridDim.x * blockDim.x)
+    write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b,
+                a.pk[static_cast<size_t>(c) * a.nb + b], a.tau[c], static_cast<double>(a.m));
+}
+
 // ---------------------------------------------------------------- y-pass
-// Workgroup = NPEN consecutive contiguous y pencils (index kz * N + ix).
+// Workgroup = NPEN consecutive contiguous y pencils (index kz * N + ix).  The
+// inverse pass also carries the sweep's P(k) step: its first nb workgroups of
+// every chain draw one bin each (the x-pass partials are complete when it
+// starts, and the new P is first read by the next sweep's x-pass).
 template <typename R, int N, bool INV>
 __global__ void __launch_bounds__((YTile<R, N>::NT))
 ypass_kernel(SweepArgs<R> a) {
@@ -279,9 +338,18 @@ ypass_kernel(SweepArgs<R> a) {
   constexpr int NT = T::NT, EPT = T::EPT;
   __shared__ cx<R> lds[T::NPEN * T::PSTR];
   __shared__ cx<R> tw[N];
+  static_assert(T::NPEN * T::PSTR * sizeof(cx<R>) >= NT * sizeof(double), "reduction space");
+  int blk = blockIdx.x;
+  if (INV) {
+    if (blk < a.nb) {
+      pk_draw_block<R, NT>(a, blk, blockIdx.z, reinterpret_cast<double*>(lds));
+      return;
+    }
+    blk -= a.nb;
+  }
   const int tid = threadIdx.x;
   cx<R>* base = a.spec + static_cast<size_t>(blockIdx.z) * a.spec_stride +
-                static_cast<size_t>(blockIdx.x) * T::NPEN * N;
+                static_cast<size_t>(blk) * T::NPEN * N;
   load_twiddles(tw, a.tw, N, NT);
   cx<R> v[EPT];
 #pragma unroll
@@ -335,9 +403,9 @@ xpass_kernel(SweepArgs<R> a) {
   constexpr int NSL = N / RL;
   __shared__ cx<R> lds[P * T::PSTR];
   __shared__ cx<R> tw[N];
-  extern __shared__ double dyn[];      // hist[NWAVES][nb], table (2 nb R), qthr (nb)
+  extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb)
   double* hist = dyn;
-  R* tab = reinterpret_cast<R*>(hist + T::NWAVES * a.nb);
+  R* tab = reinterpret_cast<R*>(hist + T::NHIST * a.nb);
   int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * a.nb);
 
   const int tid = threadIdx.x;
@@ -348,7 +416,7 @@ xpass_kernel(SweepArgs<R> a) {
                 static_cast<size_t>(kz) * N * N;
   const int nb = a.nb;
   load_twiddles(tw, a.tw, N, NT);
-  for (int i = tid; i < T::NWAVES * nb; i += NT) hist[i] = 0.0;
+  for (int i = tid; i < T::NHIST * nb; i += NT) hist[i] = 0.0;
   for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
   for (int i = tid; i < nb; i += NT) qthr[i] = a.qthr[i];
   cx<R> v[EPT];
@@ -365,7 +433,7 @@ xpass_kernel(SweepArgs<R> a) {
   const double wgt = herm ? 1.0 : 2.0;
   const float qscale = static_cast<float>(4.0 * nb * nb / (3.0 * N * N));
   const uint32_t chain = a.chain0 + c;
-  double* my_hist = hist + (tid / 64) * nb;
+  double* my_hist = hist + ((tid / 64) * T::HG + (tid % T::HG)) * nb;
 #pragma unroll
   for (int i = 0; i < EPT / RL; ++i) {
     int col = 0, q = 0;
@@ -392,7 +460,8 @@ xpass_kernel(SweepArgs<R> a) {
         cx<R> out{R(0), R(0)};
         if (qq > 0) {
           const int b = bin_of(qq, qthr, nb, qscale);
-          const R A = tab[2 * b], B = tab[2 * b + 1];
+          const cx<R> ab = reinterpret_cast<const cx<R>*>(tab)[b];
+          const R A = ab.x, B = ab.y;
           const cx<R> t = v[e];
           R gre = g[2 * h], gim = g[2 * h + 1];
           bool selfconj = false;
@@ -433,65 +502,9 @@ xpass_kernel(SweepArgs<R> a) {
   double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
   for (int b = tid; b < nb; b += NT) {
     double s = 0.0;
-    for (int w = 0; w < T::NWAVES; ++w) s += hist[w * nb + b];
+    for (int w = 0; w < T::NHIST; ++w) s += hist[w * nb + b];
     part[static_cast<size_t>(b) * a.n_wg_x] = s;
   }
-}
-
-// ---------------------------------------------------------------- P(k)
-// Per-bin table of the signal draw from P (grid units), in FP64.
-template <typename R>
-__device__ __forceinline__ void write_table(R* tab, int b, double p, double tau, double m) {
-  const double f = p / (p + tau);
-  tab[2 * b] = static_cast<R>(f / m);
-  tab[2 * b + 1] = static_cast<R>(sqrt(tau * f / (2.0 * m)));
-}
-
-// Workgroup = one (bin, chain).  Sums the x-pass partials in a fixed order
-// (strided per thread, then a tree), forms sigma_b = M^2 sum w |s^/M|^2, and
-// draws P_b = sigma_b / (2 M g), g ~ Gamma(n_b / 2, 1): the inverse-gamma
-// conditional of P_b under Jeffreys' prior.  Then refreshes (A_b, B_b).
-constexpr int kPkThreads = 256;
-
-template <typename R>
-__global__ void __launch_bounds__(kPkThreads) pk_draw_kernel(SweepArgs<R> a) {
-  __shared__ double red[kPkThreads];
-  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-  const double* part = a.partials + (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x;
-  double s = 0.0;
-  for (int w = tid; w < a.n_wg_x; w += kPkThreads) s += part[w];
-  red[tid] = s;
-  __syncthreads();
-  for (int h = kPkThreads / 2; h > 0; h >>= 1) {
-    if (tid < h) red[tid] += red[tid + h];
-    __syncthreads();
-  }
-  if (tid != 0) return;
-  const double m = static_cast<double>(a.m);
-  const double sigma = red[0] * m * m;
-  const double tau = a.tau[c];
-  double* pk = a.pk + static_cast<size_t>(c) * a.nb;
-  double p = pk[b];
-  if (a.sample_pk && a.counts[b] > 0.0) {
-    const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.sweep,
-                              a.chain0 + c, a.key0, a.key1);
-    p = sigma / (2.0 * m * g);
-    if (!(g > 0.0) || !isfinite(p) || !isfinite(sigma)) {
-      atomicOr(a.status + c, 1u);
-      p = pk[b];
-    }
-    pk[b] = p;
-  }
-  write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b, p, tau, m);
-}
-
-// Table from the current P of every chain (set-up and state restore).
-template <typename R>
-__global__ void pk_table_kernel(SweepArgs<R> a) {
-  const int c = blockIdx.y;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < a.nb; b += gridDim.x * blockDim.x)
-    write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b,
-                a.pk[static_cast<size_t>(c) * a.nb + b], a.tau[c], static_cast<double>(a.m));
 }
 
 }  // namespace mf

@@ -68,7 +68,7 @@ def test_z_and_y_transforms(precision):
     spec_y = binding.mf_debug_spectrum(g.handle, 0, n)
     ref_y = np.fft.fft(ref, axis=2)
     assert np.abs(spec_y - ref_y).max() < tol * np.abs(ref_y).max()
-    binding.mf_debug_run_kernel(g.handle, 4, 0)                 # inverse y-DFT
+    binding.mf_debug_run_kernel(g.handle, 3, 0)                 # inverse y-DFT
     spec_b = binding.mf_debug_spectrum(g.handle, 0, n)
     assert np.abs(spec_b / n - ref).max() < tol * scale
     g.close()
