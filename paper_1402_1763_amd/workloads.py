@@ -102,7 +102,7 @@ def gaussian_field(w: Workload, rng: np.random.Generator) -> np.ndarray:
     """Real field whose unnormalised DFT has E|s_k|^2 = M P(k) / V_cell."""
     white = rng.standard_normal((w.n, w.n, w.n))
     p_grid = power_spectrum(wavenumber_grid(w.n, w.box, half=True), w) / w.cell_volume
-    return np.fft.irfftn(np.fft.rfftn(white) * np.sqrt(p_grid), s=(w.n,) * 3)
+    return np.fft.irfftn(np.fft.rfftn(white) * np.sqrt(p_grid), s=(w.n,) * 3, axes=(0, 1, 2))
 
 
 def voxel_centres(w: Workload):
