@@ -145,7 +145,9 @@ mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out);
  * (to_device = 0) or from (to_device = 1) the host array `buf` of
  * 2 * (N/2 + 1) * N * N doubles, laid out [kz][ix][iy][re, im] with
  * kz in [0, N/2] -- the buffer holds the field transformed along whichever
- * axes the passes run so far have transformed.  Synchronises `stream`. */
+ * axes the passes run so far have transformed (for 32 <= N <= 256 the
+ * y-passes also run half of the x transform, so after kernel 1 the rows of a
+ * kz plane hold that intermediate).  Synchronises `stream`. */
 mf_status mf_debug_run_kernel(mf_problem* p, int32_t kernel, uint64_t sweep, void* stream);
 mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t to_device,
                             void* stream);

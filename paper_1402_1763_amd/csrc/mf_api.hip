@@ -46,25 +46,26 @@ bool supported(int n) {
 
 template <typename R, int N>
 struct Geometry {
-  static constexpr int zp = mf::ZTile<R, N>::P;
-  static constexpr int ynpen = mf::YTile<R, N>::NPEN;
-  static constexpr int xp = mf::XTile<R, N>::P;
-  static constexpr int xnwaves = mf::XTile<R, N>::NWAVES;
+  static constexpr int columns() {
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N>::P;
+    else return mf::XTile<R, N>::P;
+  }
+  static constexpr int xp = columns();
 };
 
 struct Shape {
-  int zp, ynpen, xp, xnwaves;
+  int xp;   // columns per x-pass workgroup
 };
 
 template <typename R>
 Shape shape_of(int n) {
   switch (n) {
 #define MF_SHAPE(NN) \
-  case NN: return Shape{Geometry<R, NN>::zp, Geometry<R, NN>::ynpen, Geometry<R, NN>::xp, Geometry<R, NN>::xnwaves};
+  case NN: return Shape{Geometry<R, NN>::xp};
     MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(64) MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
 #undef MF_SHAPE
   }
-  return Shape{0, 0, 0, 0};
+  return Shape{0};
 }
 
 struct Layout {
@@ -218,10 +219,11 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
   using ZT = mf::ZTile<R, N>;
   using YT = mf::YTile<R, N>;
   using XT = mf::XTile<R, N>;
+  using YS = mf::YSTile<R, N>;
+  using XS = mf::XSTile<R, N>;
+  constexpr bool split = mf::split_x<N>();
   const dim3 zgrid(N / ZT::P, N, nch), zgrid1(N / ZT::P, N, 1);
-  const dim3 ygrid((N / 2 + 1) * N / YT::NPEN, 1, nch);
-  const dim3 yigrid((N / 2 + 1) * N / YT::NPEN + a.nb, 1, nch);
-  const dim3 xgrid(N / XT::P, N / 2 + 1, nch);
+  const size_t tables = 2 * a.nb * sizeof(R) + a.nb * 4;
   switch (id) {
     case kZ:
       hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZSweep>), zgrid, dim3(ZT::NT), 0, st, a);
@@ -233,16 +235,29 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZGetState>), zgrid1, dim3(ZT::NT), 0, st, a);
       break;
     case kYF:
-      hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), ygrid, dim3(YT::NT), 0, st, a);
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 * (N / 2 + 1), 1, nch),
+                           dim3(YS::NT), 0, st, a);
+      else
+        hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), dim3((N / 2 + 1) * N / YT::NPEN, 1, nch),
+                           dim3(YT::NT), 0, st, a);
       break;
     case kYI:
-      hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>), yigrid, dim3(YT::NT), 0, st, a);
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, true>), dim3(16 * (N / 2 + 1) + a.nb, 1, nch),
+                           dim3(YS::NT), 0, st, a);
+      else
+        hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>),
+                           dim3((N / 2 + 1) * N / YT::NPEN + a.nb, 1, nch), dim3(YT::NT), 0, st, a);
       break;
-    case kX: {
-      const size_t dyn = XT::NHIST * a.nb * sizeof(double) + 2 * a.nb * sizeof(R) + a.nb * 4;
-      hipLaunchKernelGGL((mf::xpass_kernel<R, N>), xgrid, dim3(XT::NT), dyn, st, a);
+    case kX:
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N>), dim3(N / XS::P, N / 2 + 1, nch), dim3(XS::NT),
+                           XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+      else
+        hipLaunchKernelGGL((mf::xpass_kernel<R, N>), dim3(N / XT::P, N / 2 + 1, nch), dim3(XT::NT),
+                           XT::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
-    }
     case kTable:
       hipLaunchKernelGGL((mf::pk_table_kernel<R>), dim3((a.nb + 63) / 64, nch), dim3(64), 0, st, a);
       break;

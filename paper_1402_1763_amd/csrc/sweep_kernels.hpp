@@ -12,10 +12,12 @@
 //
 // One sweep = four launches:
 //   z-pass  : inverse z-DFT (-> s), messenger draw t, forward z-DFT of t
-//   y-pass  : forward y-DFT
+//   y-pass  : forward y-DFT (and, for 32 <= N <= 256, the first half of the
+//             forward x-DFT, see "x split")
 //   x-pass  : forward x-DFT (-> t^), signal draw s^, shell sums, inverse x-DFT
-//   y-pass  : inverse y-DFT, plus the per-bin reduction of the shell sums and
-//             the inverse-gamma draw of P(k) in extra workgroups
+//   y-pass  : inverse y-DFT (and the last half of the inverse x-DFT), plus the
+//             per-bin reduction of the shell sums and the inverse-gamma draw of
+//             P(k) in extra workgroups
 // The signal draw folds the inverse transform's 1/M into s^, so the stored
 // field is s^/M and every DFT is unnormalised.
 #pragma once
@@ -367,6 +369,121 @@ ypass_kernel(SweepArgs<R> a) {
   }
 }
 
+// ---------------------------------------------------------------- x split
+// For 32 <= N <= 256 the x transform is split in two (N = 16 NA, ix = q + 16 r
+// with q < 16, r < NA; k = k1 + NA k2):
+//   stage A, in the y-passes:  Y[q][k1] = W_N^{q k1} sum_r x[q + 16 r] W_NA^{r k1}
+//   stage B, in the x-pass:    X[k1 + NA k2] = sum_q Y[q][k1] W_16^{q k2}
+// Between them spec holds Y[q][k1] in row q + 16 k1 of each kz plane (the
+// rows the forward y-pass workgroup of q read, so every pass stays in place).
+// The x-pass then transforms 16 consecutive rows per thread entirely in
+// registers, and the y-passes, which have arithmetic to spare, absorb the
+// twiddles and the other half of the x transform.
+template <int N>
+__host__ __device__ constexpr bool split_x() { return N >= 32 && N <= 256; }
+
+// Forward y-pass with x stage A (INV = false), or inverse x stage A with the
+// inverse y-pass (INV = true, plus the P(k) step in the first nb workgroups).
+// Workgroup = one (kz, q): the NA y pencils of rows ix = q + 16 r.
+template <typename R, int N>
+struct YSTile {
+  static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
+  static constexpr int EPT = 16;
+  static constexpr int NT = NA * N / EPT;
+  static constexpr int COLS = 16 / NA;     // columns per thread in the x-stage layout
+  static constexpr int PADS = ilog2(Radices<N>::r[0]);
+  static constexpr int PSTR = N + (N >> PADS);
+  using TL = Tile<N, NA, NT, false, PSTR, PADS>;
+};
+
+template <typename R, int N, bool INV>
+__global__ void __launch_bounds__((YSTile<R, N>::NT))
+ysplit_kernel(SweepArgs<R> a) {
+  using T = YSTile<R, N>;
+  using TL = typename T::TL;
+  constexpr int NA = T::NA, NT = T::NT, EPT = T::EPT, COLS = T::COLS;
+  __shared__ cx<R> lds[NA * T::PSTR];
+  __shared__ cx<R> tw[N];
+  static_assert(NA * T::PSTR * sizeof(cx<R>) >= NT * sizeof(double), "reduction space");
+  int blk = blockIdx.x;
+  if (INV) {
+    if (blk < a.nb) {
+      pk_draw_block<R, NT>(a, blk, blockIdx.z, reinterpret_cast<double*>(lds));
+      return;
+    }
+    blk -= a.nb;
+  }
+  const int tid = threadIdx.x;
+  const int kz = blk / 16, q = blk % 16;
+  cx<R>* plane = a.spec + static_cast<size_t>(blockIdx.z) * a.spec_stride +
+                 static_cast<size_t>(kz) * N * N;
+  load_twiddles(tw, a.tw, N, NT);
+  cx<R> v[EPT];
+  if (!INV) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int pen = 0, n = 0;
+      TL::template in_pos<false>(tid, e, pen, n);
+      v[e] = plane[static_cast<size_t>(q + 16 * pen) * N + n];
+    }
+    fft_regs<R, N, TL, NT, false, false>(v, lds, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int pen = 0, n = 0;
+      TL::template out_pos<false>(tid, e, pen, n);
+      lds[TL::lidx(pen, n)] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < COLS; ++j) {
+      const int iy = tid + j * NT;
+      cx<R>* u = v + j * NA;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) u[r] = lds[TL::lidx(r, iy)];
+      dft<R, NA, false>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < NA; ++k1) {
+        const cx<R> w = k1 ? cmul(u[k1], tw[q * k1]) : u[k1];
+        plane[static_cast<size_t>(q + 16 * k1) * N + iy] = w;
+      }
+    }
+  } else {
+    __syncthreads();   // twiddles in LDS
+#pragma unroll
+    for (int j = 0; j < COLS; ++j) {
+      const int iy = tid + j * NT;
+      cx<R>* u = v + j * NA;
+#pragma unroll
+      for (int k1 = 0; k1 < NA; ++k1) {
+        const cx<R> w = plane[static_cast<size_t>(q + 16 * k1) * N + iy];
+        u[k1] = k1 ? cmulc(w, tw[q * k1]) : w;
+      }
+      dft<R, NA, true>(u);
+    }
+#pragma unroll
+    for (int j = 0; j < COLS; ++j) {
+#pragma unroll
+      for (int r = 0; r < NA; ++r) lds[TL::lidx(r, tid + j * NT)] = v[j * NA + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int pen = 0, n = 0;
+      TL::template in_pos<false>(tid, e, pen, n);
+      v[e] = lds[TL::lidx(pen, n)];
+    }
+    __syncthreads();   // the transform below rewrites the buffer
+    fft_regs<R, N, TL, NT, true, false>(v, lds, tw);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int pen = 0, n = 0;
+      TL::template out_pos<false>(tid, e, pen, n);
+      plane[static_cast<size_t>(q + 16 * pen) * N + n] = v[e];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- x-pass
 __device__ __forceinline__ int wavenumber(int i, int n) { return i <= n / 2 ? i : i - n; }
 
@@ -379,9 +496,19 @@ __device__ __forceinline__ int bin_of(int q, const int32_t* qthr, int nb, float 
   return b;
 }
 
-// Workgroup = one kz plane and P consecutive iy columns; x pencils are the
-// columns.  After the forward x-DFT a thread holds t^ of modes (ix, iy, kz)
-// with ix = q + (N/R_L) r; each is drawn from the signal conditional
+template <typename R>
+struct DrawCtx {
+  const int32_t* qthr;    // LDS
+  const cx<R>* tab;       // LDS, (A_b, B_b)
+  double* hist;           // this lane's LDS histogram
+  float qscale;
+  int nb;
+  uint32_t chain;
+};
+
+// Signal draw of one register slot: v[r] holds t^ of mode (ix, iy, kz) with
+// ix = q + S r, r < RL (S RL = N).  Each mode is drawn from the signal
+// conditional
 //   s^ = f t^ + sqrt(v/2) (G_re + i G_im),  f = P/(P + tau), v = M tau f,
 // stored divided by M: s^/M = A_b t^ + B_b (G_re + i G_im), A_b = f/M,
 // B_b = sqrt(tau f / (2M)).  Self-conjugate modes are real with the full
@@ -389,36 +516,186 @@ __device__ __forceinline__ int bin_of(int q, const int32_t* qthr, int nb, float 
 // with the larger ix*N + iy uses its partner's normals conjugated; q = 0
 // gives 0.  (G_re, G_im) of (ix, iy, kz) come from Philox counter
 // ((kz N + iy) N/2 + ix mod N/2, sweep, 1, chain): words (x0, x1) for
-// ix < N/2, (x2, x3) for ix >= N/2.  Shell sums of w |s^/M|^2 (w = 1 on
-// kz = 0, N/2, else 2) go to per-wave LDS histograms (a wave's atomics land in
-// a fixed order), then to one partial per workgroup.  The inverse x-DFT runs
-// in the reversed radix order so it starts from the same registers.
+// ix < N/2, (x2, x3) for ix >= N/2 -- modes r and r + RL/2 share a call.
+// w |s^/M|^2 (w = 1 on kz = 0, N/2, else 2) is added to the lane's LDS
+// histogram.
+template <typename R, int N, int RL, int S>
+__device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
+                                          const SweepArgs<R>& a, const DrawCtx<R>& d) {
+  constexpr int H = N / 2;
+  const bool herm = (kz == 0 || kz == H);
+  const double wgt = herm ? 1.0 : 2.0;
+  const int my = wavenumber(iy, N);
+  const int r2 = my * my + kz * kz;
+  const int py = (N - iy) & (N - 1);
+#pragma unroll
+  for (int r = 0; r < RL / 2; ++r) {
+    const int ixl = q + S * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
+    R g[4];
+    {
+      const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
+      const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
+      box_muller(w.x0, w.x1, g[0], g[1]);
+      box_muller(w.x2, w.x3, g[2], g[3]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = r + h * (RL / 2);
+      const int x = ixl + h * H;
+      const int mx = wavenumber(x, N);
+      const int qq = mx * mx + r2;
+      const int plin = ((N - x) & (N - 1)) * N + py, lin = x * N + iy;
+      if (herm && plin < lin) continue;   // drawn in the second loop
+      cx<R> out{R(0), R(0)};
+      if (qq > 0) {
+        const int b = bin_of(qq, d.qthr, d.nb, d.qscale);
+        const cx<R> ab = d.tab[b];
+        const cx<R> t = v[e];
+        if (herm && plin == lin)   // self-conjugate: real, full variance
+          out = cx<R>{ab.x * t.x + R(1.4142135623730950488) * ab.y * g[2 * h], R(0)};
+        else
+          out = cx<R>{ab.x * t.x + ab.y * g[2 * h], ab.x * t.y + ab.y * g[2 * h + 1]};
+        const double ox = static_cast<double>(out.x), oy = static_cast<double>(out.y);
+        atomicAdd(d.hist + b, wgt * (ox * ox + oy * oy));
+      }
+      v[e] = out;
+    }
+  }
+  if (herm) {
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int x = q + S * e;
+      const int px = (N - x) & (N - 1);
+      if (px * N + py >= x * N + iy) continue;
+      const int mx = wavenumber(x, N);
+      const int b = bin_of(mx * mx + r2, d.qthr, d.nb, d.qscale);
+      const cx<R> ab = d.tab[b];
+      const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px & (H - 1)));
+      const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
+      R g0, g1;
+      if (px >= H) box_muller(w.x2, w.x3, g0, g1);
+      else box_muller(w.x0, w.x1, g0, g1);
+      const cx<R> t = v[e];
+      const cx<R> out{ab.x * t.x + ab.y * g0, ab.x * t.y - ab.y * g1};
+      const double ox = static_cast<double>(out.x), oy = static_cast<double>(out.y);
+      atomicAdd(d.hist + b, wgt * (ox * ox + oy * oy));
+      v[e] = out;
+    }
+  }
+}
+
+// Shared prologue / epilogue of the x-pass kernels: LDS tables and per-wave
+// histograms (HG copies per wave by lane), then one partial per workgroup.
+template <typename R, int NT, int NHIST, int HG>
+__device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c, double* dyn,
+                                                    int n) {
+  const int nb = a.nb, tid = threadIdx.x;
+  double* hist = dyn;
+  R* tab = reinterpret_cast<R*>(hist + NHIST * nb);
+  int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * nb);
+  for (int i = tid; i < NHIST * nb; i += NT) hist[i] = 0.0;
+  for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
+  for (int i = tid; i < nb; i += NT) qthr[i] = a.qthr[i];
+  DrawCtx<R> d;
+  d.qthr = qthr;
+  d.tab = reinterpret_cast<const cx<R>*>(tab);
+  d.hist = hist + ((tid / 64) * HG + (tid % HG)) * nb;
+  d.qscale = static_cast<float>(4.0 * nb * nb / (3.0 * n * n));
+  d.nb = nb;
+  d.chain = a.chain0 + c;
+  return d;
+}
+
+template <typename R, int NT, int NHIST>
+__device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, double* hist, int wg) {
+  __syncthreads();   // all histogram atomics are done
+  const int nb = a.nb, tid = threadIdx.x;
+  double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
+  // Fixed-order reduction of the NHIST copies: G groups of PER consecutive
+  // copies, each summed in ascending order into its first copy (every entry is
+  // read and written by one thread only), then the G group sums in order.
+  constexpr int G = NHIST >= 16 ? 8 : 1;
+  constexpr int PER = NHIST / G;
+  if (G > 1) {
+    for (int it = tid; it < nb * G; it += NT) {
+      const int b = it % nb, g = it / nb;
+      double s = 0.0;
+      for (int w = 0; w < PER; ++w) s += hist[(g * PER + w) * nb + b];
+      hist[g * PER * nb + b] = s;
+    }
+    __syncthreads();
+  }
+  // group sums sit at copies 0, PER, 2 PER, ...; with one group, every copy
+  constexpr int STEP = G > 1 ? PER : 1;
+  constexpr int COUNT = G > 1 ? G : NHIST;
+  for (int b = tid; b < nb; b += NT) {
+    double s = 0.0;
+    for (int g = 0; g < COUNT; ++g) s += hist[g * STEP * nb + b];
+    part[static_cast<size_t>(b) * a.n_wg_x] = s;
+  }
+}
+
+// Split x-pass (32 <= N <= 256): workgroup = one kz plane and P consecutive iy
+// columns; thread (col, k1) holds rows 16 k1 .. 16 k1 + 15 of its column,
+// i.e. Y[0..15][k1], and runs x stage B, the draw and the inverse stage B in
+// registers.
+template <typename R, int N>
+struct XSTile {
+  static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
+  static constexpr int P = (256 / NA) > N ? N : 256 / NA;   // columns per workgroup
+  static constexpr int NT = P * NA;
+  static constexpr int HG = 2;
+  static constexpr int NHIST = ((NT + 63) / 64) * HG;
+};
+
+template <typename R, int N>
+__global__ void __launch_bounds__((XSTile<R, N>::NT))
+xsplit_kernel(SweepArgs<R> a) {
+  using T = XSTile<R, N>;
+  constexpr int P = T::P, NT = T::NT, NA = T::NA;
+  extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb)
+  const int tid = threadIdx.x;
+  const int iy0 = blockIdx.x * P;
+  const int kz = blockIdx.y;
+  const int c = blockIdx.z;
+  const DrawCtx<R> d = draw_prologue<R, NT, T::NHIST, T::HG>(a, c, dyn, N);
+  const int col = tid % P, k1 = tid / P;
+  cx<R>* base = a.spec + static_cast<size_t>(c) * a.spec_stride +
+                (static_cast<size_t>(kz) * N + 16 * k1) * N + iy0 + col;
+  cx<R> v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = base[static_cast<size_t>(j) * N];
+  dft<R, 16, false>(v);                 // v[k2] = X[k1 + NA k2]
+  __syncthreads();                      // tables and histograms ready
+  draw_slot<R, N, 16, NA>(v, k1, iy0 + col, kz, a, d);
+  dft<R, 16, true>(v);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) base[static_cast<size_t>(j) * N] = v[j];
+  draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// Whole-transform x-pass (N = 8, 16, 512): workgroup = one kz plane and P
+// consecutive iy columns; forward x-DFT, draw, inverse x-DFT (in the reversed
+// radix order, so it starts from the same registers).
 template <typename R, int N>
 __global__ void __launch_bounds__((XTile<R, N>::NT))
 xpass_kernel(SweepArgs<R> a) {
   using T = XTile<R, N>;
   using TL = typename T::TL;
-  constexpr int P = T::P, NT = T::NT, EPT = T::EPT, H = N / 2;
+  constexpr int P = T::P, NT = T::NT, EPT = T::EPT;
   constexpr int RL = radix_at<N, false>(Radices<N>::n - 1);
   constexpr int NSL = N / RL;
   __shared__ cx<R> lds[P * T::PSTR];
   __shared__ cx<R> tw[N];
-  extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb)
-  double* hist = dyn;
-  R* tab = reinterpret_cast<R*>(hist + T::NHIST * a.nb);
-  int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * a.nb);
-
+  extern __shared__ double dyn[];
   const int tid = threadIdx.x;
   const int iy0 = blockIdx.x * P;
   const int kz = blockIdx.y;
   const int c = blockIdx.z;
   cx<R>* spec = a.spec + static_cast<size_t>(c) * a.spec_stride +
                 static_cast<size_t>(kz) * N * N;
-  const int nb = a.nb;
   load_twiddles(tw, a.tw, N, NT);
-  for (int i = tid; i < T::NHIST * nb; i += NT) hist[i] = 0.0;
-  for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
-  for (int i = tid; i < nb; i += NT) qthr[i] = a.qthr[i];
+  const DrawCtx<R> d = draw_prologue<R, NT, T::NHIST, T::HG>(a, c, dyn, N);
   cx<R> v[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -428,66 +705,11 @@ xpass_kernel(SweepArgs<R> a) {
   }
   __syncthreads();   // tables and histograms ready (single-stage sizes have no barrier)
   fft_regs<R, N, TL, NT, false, false>(v, lds, tw);
-
-  const bool herm = (kz == 0 || kz == H);
-  const double wgt = herm ? 1.0 : 2.0;
-  const float qscale = static_cast<float>(4.0 * nb * nb / (3.0 * N * N));
-  const uint32_t chain = a.chain0 + c;
-  double* my_hist = hist + ((tid / 64) * T::HG + (tid % T::HG)) * nb;
 #pragma unroll
   for (int i = 0; i < EPT / RL; ++i) {
     int col = 0, q = 0;
     TL::split(tid + i * NT, NSL, col, q);
-    const int iy = iy0 + col;
-    const int my = wavenumber(iy, N);
-    const int r2 = my * my + kz * kz;
-#pragma unroll
-    for (int r = 0; r < RL / 2; ++r) {
-      const int ixl = q + NSL * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
-      R g[4];
-      {
-        const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
-        const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, chain, a.key0, a.key1);
-        box_muller(w.x0, w.x1, g[0], g[1]);
-        box_muller(w.x2, w.x3, g[2], g[3]);
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int e = i * RL + r + h * (RL / 2);
-        const int x = ixl + h * H;
-        const int mx = wavenumber(x, N);
-        const int qq = mx * mx + r2;
-        cx<R> out{R(0), R(0)};
-        if (qq > 0) {
-          const int b = bin_of(qq, qthr, nb, qscale);
-          const cx<R> ab = reinterpret_cast<const cx<R>*>(tab)[b];
-          const R A = ab.x, B = ab.y;
-          const cx<R> t = v[e];
-          R gre = g[2 * h], gim = g[2 * h + 1];
-          bool selfconj = false;
-          if (herm) {
-            const int px = (N - x) & (N - 1), py = (N - iy) & (N - 1);
-            const int lin = x * N + iy, plin = px * N + py;
-            if (plin == lin) {
-              selfconj = true;
-            } else if (plin < lin) {
-              const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px & (H - 1)));
-              const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, chain, a.key0, a.key1);
-              R h0, h1;
-              if (px >= H) box_muller(w.x2, w.x3, h0, h1);
-              else box_muller(w.x0, w.x1, h0, h1);
-              gre = h0;
-              gim = -h1;
-            }
-          }
-          if (selfconj) out = cx<R>{A * t.x + R(1.4142135623730950488) * B * gre, R(0)};
-          else out = cx<R>{A * t.x + B * gre, A * t.y + B * gim};
-          const double ox = static_cast<double>(out.x), oy = static_cast<double>(out.y);
-          atomicAdd(my_hist + b, wgt * (ox * ox + oy * oy));
-        }
-        v[e] = out;
-      }
-    }
+    draw_slot<R, N, RL, NSL>(v + i * RL, q, iy0 + col, kz, a, d);
   }
   __syncthreads();   // every lane is done with the forward transform's LDS reads
   fft_regs<R, N, TL, NT, true, true>(v, lds, tw);
@@ -497,14 +719,7 @@ xpass_kernel(SweepArgs<R> a) {
     TL::template out_pos<true>(tid, e, col, ix);
     spec[static_cast<size_t>(ix) * N + iy0 + col] = v[e];
   }
-  __syncthreads();   // all histogram atomics are done
-  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-  double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
-  for (int b = tid; b < nb; b += NT) {
-    double s = 0.0;
-    for (int w = 0; w < T::NHIST; ++w) s += hist[w * nb + b];
-    part[static_cast<size_t>(b) * a.n_wg_x] = s;
-  }
+  draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 }  // namespace mf
