@@ -135,12 +135,27 @@ mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double
 mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, const double* pk,
                              uint64_t sweep, void* stream);
 
+/* Checkpoints: the exact device state of one chain (its half-complex field in
+ * the working precision, P per bin in FP64, and the sweep index), so that a
+ * chain resumed from a checkpoint continues bitwise identically -- the random
+ * numbers carry no state beyond the sweep index.  mf_checkpoint_bytes gives
+ * the size of one chain's checkpoint; mf_save_checkpoint writes it to the
+ * host buffer `buf` (synchronises `stream`); mf_load_checkpoint restores it
+ * into chain `chain` of a problem with the same N, n_bins and precision, and
+ * sets the problem's sweep counter to the checkpoint's.
+ * Errors: MF_E_INVALID_ARG (size or header mismatch), MF_E_STATE, MF_E_DEVICE. */
+mf_status mf_checkpoint_bytes(mf_problem* p, size_t* bytes);
+mf_status mf_save_checkpoint(mf_problem* p, int32_t chain, void* buf, size_t bytes, void* stream);
+mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size_t bytes,
+                             void* stream);
+
 /* The messenger variance tau of a chain (host value). */
 mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out);
 
 /* Diagnostics (used by the tests to check single passes).
  * mf_debug_run_kernel: enqueue one sweep kernel (numbering as in
- * MF_NUM_KERNELS) for every chain with sweep index `sweep`.
+ * MF_NUM_KERNELS) for every chain with sweep index `sweep` (it rewrites the
+ * device sweep counter; reset it with mf_set_chain_state before sweeping).
  * mf_debug_spectrum: copy chain `chain`'s half-complex working buffer to
  * (to_device = 0) or from (to_device = 1) the host array `buf` of
  * 2 * (N/2 + 1) * N * N doubles, laid out [kz][ix][iy][re, im] with
@@ -151,6 +166,21 @@ mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out);
 mf_status mf_debug_run_kernel(mf_problem* p, int32_t kernel, uint64_t sweep, void* stream);
 mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t to_device,
                             void* stream);
+
+/* Graphs of sweeps, for batches of problems (different grid sizes or
+ * precisions) run as independent chains (Sec. 3.4: independent chains need no
+ * communication).  mf_graph_create captures one Gibbs sweep of each of the n
+ * problems into one HIP graph; problems are independent branches of the graph
+ * and may run concurrently.  mf_graph_launch replays it n_sweeps times on
+ * `stream` (asynchronously) and advances every problem's sweep counter; the
+ * replays draw the same random numbers as mf_gibbs_sweep would.  The problems
+ * must outlive the graph and must not be swept on another stream while a
+ * replay is in flight.  The graph owns its side streams and events.
+ * Errors: MF_E_INVALID_ARG, MF_E_DEVICE. */
+typedef struct mf_graph mf_graph;
+mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, mf_graph** out);
+mf_status mf_graph_launch(mf_graph* g, int32_t n_sweeps, void* stream);
+void mf_graph_destroy(mf_graph* g);
 
 /* Release the handle (not the workspace).  NULL is ignored. */
 void mf_destroy_problem(mf_problem* p);

@@ -70,6 +70,15 @@ SIGNATURES = {
                                            ctypes.c_void_p]),
     "mf_debug_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
                                          ctypes.c_int32, ctypes.c_void_p]),
+    "mf_checkpoint_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_save_checkpoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]),
+    "mf_load_checkpoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]),
+    "mf_graph_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "mf_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "mf_graph_destroy": (None, [ctypes.c_void_p]),
     "mf_destroy_problem": (None, [ctypes.c_void_p]),
     "mf_last_error": (ctypes.c_char_p, []),
 }
@@ -219,6 +228,44 @@ def mf_debug_spectrum(handle: int, chain: int, n: int, buf: Optional[np.ndarray]
     return buf
 
 
+def mf_checkpoint_bytes(handle: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().mf_checkpoint_bytes(ctypes.c_void_p(handle), ctypes.byref(out)))
+    return out.value
+
+
+def mf_save_checkpoint(handle: int, chain: int, stream=None) -> bytes:
+    n = mf_checkpoint_bytes(handle)
+    buf = ctypes.create_string_buffer(n)
+    _check(load().mf_save_checkpoint(ctypes.c_void_p(handle), chain, buf, n,
+                                     ctypes.c_void_p(_stream_ptr(stream))))
+    return buf.raw
+
+
+def mf_load_checkpoint(handle: int, chain: int, data: bytes, stream=None):
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(load().mf_load_checkpoint(ctypes.c_void_p(handle), chain, buf, len(data),
+                                     ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mf_graph_create(handles: Sequence[int], stream=None) -> int:
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    out = ctypes.c_void_p()
+    _check(load().mf_graph_create(arr, len(handles), ctypes.c_void_p(_stream_ptr(stream)),
+                                  ctypes.byref(out)))
+    return out.value
+
+
+def mf_graph_launch(graph: int, n_sweeps: int, stream=None):
+    _check(load().mf_graph_launch(ctypes.c_void_p(graph), n_sweeps,
+                                  ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mf_graph_destroy(graph: int):
+    if graph:
+        load().mf_graph_destroy(ctypes.c_void_p(graph))
+
+
 def mf_destroy_problem(handle: int):
     if handle:
         load().mf_destroy_problem(ctypes.c_void_p(handle))
@@ -273,9 +320,41 @@ class Sampler:
     def tau(self, chain: int = 0) -> float:
         return mf_get_tau(self.handle, chain)
 
+    def save_checkpoint(self, chain: int = 0) -> bytes:
+        return mf_save_checkpoint(self.handle, chain, self.stream.cuda_stream)
+
+    def load_checkpoint(self, data: bytes, chain: int = 0):
+        mf_load_checkpoint(self.handle, chain, data, self.stream.cuda_stream)
+
     def close(self):
         if getattr(self, "handle", None):
             mf_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SweepGraph:
+    """One HIP graph that sweeps several samplers (independent chains of any
+    sizes) once per replay."""
+
+    def __init__(self, samplers: Sequence["Sampler"]):
+        import torch
+        self.samplers = list(samplers)
+        self.stream = torch.cuda.current_stream()
+        self.handle = mf_graph_create([smp.handle for smp in self.samplers],
+                                      self.stream.cuda_stream)
+
+    def launch(self, n_sweeps: int = 1):
+        mf_graph_launch(self.handle, n_sweeps, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mf_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

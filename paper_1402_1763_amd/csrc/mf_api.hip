@@ -69,7 +69,7 @@ Shape shape_of(int n) {
 }
 
 struct Layout {
-  size_t tw, qthr, counts, tau, pk, table, status, partials, coef, spec, staging, total;
+  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, coef, spec, staging, total;
   size_t spec_elems, spec_stride;
   int n_wg_x;
 };
@@ -89,6 +89,7 @@ Layout make_layout(const mf_chain_desc& d) {
     off = align_up(off + bytes);
     return at;
   };
+  L.ctr = take(2 * 4);
   L.tw = take(n * 2 * rs);
   L.qthr = take(nb * 4);
   L.counts = take(nb * 8);
@@ -199,13 +200,13 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   a.counts = reinterpret_cast<const double*>(ws + p->L.counts);
   a.tw = reinterpret_cast<const mf::cx<R>*>(ws + p->L.tw);
   a.status = reinterpret_cast<uint32_t*>(ws + p->L.status);
+  a.ctr = reinterpret_cast<uint32_t*>(ws + p->L.ctr);
   a.spec_stride = p->L.spec_stride;
   a.m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
   a.nb = p->desc.n_bins;
   a.n_wg_x = p->L.n_wg_x;
   a.staging_chain = 0;
   a.sample_pk = p->desc.sample_pk;
-  a.sweep = static_cast<uint32_t>(p->sweep);
   a.chain0 = p->desc.chain_id;
   a.key0 = static_cast<uint32_t>(p->desc.seed);
   a.key1 = static_cast<uint32_t>(p->desc.seed >> 32);
@@ -277,22 +278,28 @@ void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st) {
   }
 }
 
-mf_status launch_checked(mf_problem* p, int id, uint64_t sweep, int staging_chain,
-                         hipStream_t st) {
+mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t st) {
   const int nch = p->desc.n_chains;
   if (p->fp64()) {
     auto a = args_of<double>(p);
-    a.sweep = static_cast<uint32_t>(sweep);
     a.staging_chain = staging_chain;
     launch<double>(id, a, p->desc.n, nch, st);
   } else {
     auto a = args_of<float>(p);
-    a.sweep = static_cast<uint32_t>(sweep);
     a.staging_chain = staging_chain;
     launch<float>(id, a, p->desc.n, nch, st);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MF_E_DEVICE, "kernel %d launch failed: %s", id, hipGetErrorString(e));
+  return MF_OK;
+}
+
+// Device sweep counter := sweep (the sweep kernels read it; the last pass of
+// every sweep advances it).
+mf_status write_counter(mf_problem* p, uint64_t sweep, hipStream_t st) {
+  const uint32_t c[2] = {static_cast<uint32_t>(sweep), 0u};
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.ctr, c, sizeof(c), hipMemcpyHostToDevice, st));
+  MF_HIP(hipStreamSynchronize(st));
   return MF_OK;
 }
 
@@ -371,7 +378,7 @@ mf_status set_state(mf_problem* p, int chain, const double* s, const double* pk,
   if (s) {
     mf_status r = upload_real(p, p->ws + p->L.staging, s, m, st);
     if (r != MF_OK) return r;
-    r = launch_checked(p, kZSet, p->sweep, chain, st);
+    r = launch_checked(p, kZSet, chain, st);
     if (r != MF_OK) return r;
   }
   if (pk) {
@@ -385,7 +392,7 @@ mf_status set_state(mf_problem* p, int chain, const double* s, const double* pk,
     MF_HIP(hipMemcpyAsync(p->ws + p->L.pk + static_cast<size_t>(chain) * p->desc.n_bins * 8,
                           pg.data(), pg.size() * 8, hipMemcpyHostToDevice, st));
     MF_HIP(hipStreamSynchronize(st));
-    mf_status r = launch_checked(p, kTable, p->sweep, chain, st);
+    mf_status r = launch_checked(p, kTable, chain, st);
     if (r != MF_OK) return r;
   }
   (void)rs;
@@ -480,6 +487,7 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
       hipMemcpyAsync(p->ws + L.counts, counts.data(), nb * 8, hipMemcpyHostToDevice, hs) != hipSuccess ||
       hipMemcpyAsync(p->ws + L.tau, tau.data(), nch * 8, hipMemcpyHostToDevice, hs) != hipSuccess ||
       hipMemsetAsync(p->ws + L.status, 0, nch * 4, hs) != hipSuccess ||
+      hipMemsetAsync(p->ws + L.ctr, 0, 8, hs) != hipSuccess ||
       hipMemsetAsync(p->ws + L.partials, 0, static_cast<size_t>(nch) * L.n_wg_x * nb * 8, hs) != hipSuccess ||
       hipStreamSynchronize(hs) != hipSuccess)
     return cleanup(fail(MF_E_DEVICE, "uploading tables failed"));
@@ -513,7 +521,7 @@ mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
   hipStream_t hs = static_cast<hipStream_t>(stream);
   for (int i = 0; i < n_sweeps; ++i) {
     for (int k = 0; k < MF_NUM_KERNELS; ++k) {
-      const mf_status st = launch_checked(p, kSweepOrder[k], p->sweep, 0, hs);
+      const mf_status st = launch_checked(p, kSweepOrder[k], 0, hs);
       if (st != MF_OK) return st;
     }
     ++p->sweep;
@@ -533,7 +541,7 @@ mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, do
     hipEvent_t* e = &ev[static_cast<size_t>(i) * (MF_NUM_KERNELS + 1)];
     MF_HIP(hipEventRecord(e[0], hs));
     for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k) {
-      st = launch_checked(p, kSweepOrder[k], p->sweep, 0, hs);
+      st = launch_checked(p, kSweepOrder[k], 0, hs);
       if (st == MF_OK) MF_HIP(hipEventRecord(e[k + 1], hs));
     }
     ++p->sweep;
@@ -561,7 +569,7 @@ mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
   if (s_out) {
-    mf_status st = launch_checked(p, kZGet, p->sweep, chain, hs);
+    mf_status st = launch_checked(p, kZGet, chain, hs);
     if (st != MF_OK) return st;
     if ((st = download_real(p, s_out, p->ws + p->L.staging, m, hs)) != MF_OK) return st;
   }
@@ -590,7 +598,76 @@ mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, cons
     for (size_t i = 0; i < m; ++i)
       if (!std::isfinite(s[i])) return fail(MF_E_NONFINITE, "s not finite at %zu", i);
   p->sweep = sweep;
+  const mf_status st = write_counter(p, sweep, static_cast<hipStream_t>(stream));
+  if (st != MF_OK) return st;
   return set_state(p, chain, s, pk, static_cast<hipStream_t>(stream));
+}
+
+namespace {
+struct CheckpointHeader {
+  char magic[8];        // "MFGIBBS1"
+  int32_t n, n_bins, precision, reserved;
+  uint64_t sweep;
+};
+size_t checkpoint_bytes(const mf_problem* p) {
+  const size_t rs = p->fp64() ? 8 : 4;
+  return sizeof(CheckpointHeader) + p->desc.n_bins * 8 + p->L.spec_elems * 2 * rs;
+}
+}  // namespace
+
+mf_status mf_checkpoint_bytes(mf_problem* p, size_t* bytes) {
+  if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
+  *bytes = checkpoint_bytes(p);
+  return MF_OK;
+}
+
+mf_status mf_save_checkpoint(mf_problem* p, int32_t chain, void* buf, size_t bytes, void* stream) {
+  if (!p || !buf) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  if (bytes < checkpoint_bytes(p)) return fail(MF_E_INVALID_ARG, "checkpoint buffer too small");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const size_t rs = p->fp64() ? 8 : 4;
+  CheckpointHeader h{};
+  std::memcpy(h.magic, "MFGIBBS1", 8);
+  h.n = p->desc.n;
+  h.n_bins = p->desc.n_bins;
+  h.precision = p->desc.precision;
+  h.sweep = p->sweep;
+  char* out = static_cast<char*>(buf);
+  std::memcpy(out, &h, sizeof(h));
+  const int nb = p->desc.n_bins;
+  MF_HIP(hipMemcpyAsync(out + sizeof(h), p->ws + p->L.pk + static_cast<size_t>(chain) * nb * 8,
+                        nb * 8, hipMemcpyDeviceToHost, hs));
+  MF_HIP(hipMemcpyAsync(out + sizeof(h) + nb * 8,
+                        p->ws + p->L.spec + static_cast<size_t>(chain) * p->L.spec_stride * 2 * rs,
+                        p->L.spec_elems * 2 * rs, hipMemcpyDeviceToHost, hs));
+  MF_HIP(hipStreamSynchronize(hs));
+  return MF_OK;
+}
+
+mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size_t bytes,
+                             void* stream) {
+  if (!p || !buf) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  if (bytes < checkpoint_bytes(p)) return fail(MF_E_INVALID_ARG, "checkpoint buffer too small");
+  CheckpointHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, "MFGIBBS1", 8) != 0 || h.n != p->desc.n || h.n_bins != p->desc.n_bins ||
+      h.precision != p->desc.precision)
+    return fail(MF_E_INVALID_ARG, "checkpoint does not match this problem");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const size_t rs = p->fp64() ? 8 : 4;
+  const int nb = p->desc.n_bins;
+  const char* in = static_cast<const char*>(buf);
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.pk + static_cast<size_t>(chain) * nb * 8, in + sizeof(h),
+                        nb * 8, hipMemcpyHostToDevice, hs));
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.spec + static_cast<size_t>(chain) * p->L.spec_stride * 2 * rs,
+                        in + sizeof(h) + nb * 8, p->L.spec_elems * 2 * rs, hipMemcpyHostToDevice, hs));
+  MF_HIP(hipStreamSynchronize(hs));
+  mf_status st = launch_checked(p, kTable, chain, hs);
+  if (st != MF_OK) return st;
+  p->sweep = h.sweep;
+  return write_counter(p, h.sweep, hs);
 }
 
 mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out) {
@@ -603,7 +680,10 @@ mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out) {
 mf_status mf_debug_run_kernel(mf_problem* p, int32_t kernel, uint64_t sweep, void* stream) {
   if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
   if (kernel < 0 || kernel >= MF_NUM_KERNELS) return fail(MF_E_INVALID_ARG, "bad kernel id");
-  return launch_checked(p, kSweepOrder[kernel], sweep, 0, static_cast<hipStream_t>(stream));
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const mf_status st = write_counter(p, sweep, hs);
+  if (st != MF_OK) return st;
+  return launch_checked(p, kSweepOrder[kernel], 0, hs);
 }
 
 mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t to_device,
@@ -619,6 +699,93 @@ mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t t
 }
 
 void mf_destroy_problem(mf_problem* p) { delete p; }
+
+}  // extern "C"
+
+struct mf_graph {
+  std::vector<mf_problem*> probs;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~mf_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : events) (void)hipEventDestroy(e);
+    for (auto s : side) (void)hipStreamDestroy(s);
+  }
+};
+
+extern "C" {
+
+mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, mf_graph** out) {
+  if (!out) return fail(MF_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!problems || n < 1) return fail(MF_E_INVALID_ARG, "need at least one problem");
+  for (int i = 0; i < n; ++i)
+    if (!problems[i]) return fail(MF_E_INVALID_ARG, "problem %d is NULL", i);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  mf_graph* g = new mf_graph{};
+  g->probs.assign(problems, problems + n);
+  auto bail = [&](const char* what, hipError_t e) {
+    delete g;
+    return fail(MF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e;
+  for (int i = 0; i < n; ++i) {
+    hipStream_t s2;
+    if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess)
+      return bail("hipStreamCreateWithFlags", e);
+    g->side.push_back(s2);
+  }
+  for (int i = 0; i < n + 1; ++i) {
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return bail("hipEventCreate", e);
+    g->events.push_back(ev);
+  }
+  // Capture on a stream of the graph's own (the caller's may be the legacy
+  // default stream, which cannot be captured); replays go to the caller's.
+  (void)hs;
+  hipStream_t cap;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+    return bail("hipStreamCreateWithFlags", e);
+  g->side.push_back(cap);
+  hs = cap;
+  if ((e = hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return bail("hipStreamBeginCapture", e);
+  mf_status st = MF_OK;
+  (void)hipEventRecord(g->events[n], hs);             // fork point
+  for (int i = 0; i < n && st == MF_OK; ++i) {
+    hipStream_t s2 = g->side[i];
+    (void)hipStreamWaitEvent(s2, g->events[n], 0);
+    for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k)
+      st = launch_checked(problems[i], kSweepOrder[k], 0, s2);
+    (void)hipEventRecord(g->events[i], s2);
+    (void)hipStreamWaitEvent(hs, g->events[i], 0);     // join
+  }
+  e = hipStreamEndCapture(hs, &g->graph);
+  if (st != MF_OK) {
+    delete g;
+    return st;
+  }
+  if (e != hipSuccess) return bail("hipStreamEndCapture", e);
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return bail("hipGraphInstantiate", e);
+  *out = g;
+  return MF_OK;
+}
+
+mf_status mf_graph_launch(mf_graph* g, int32_t n_sweeps, void* stream) {
+  if (!g) return fail(MF_E_INVALID_ARG, "graph is NULL");
+  if (n_sweeps < 0) return fail(MF_E_INVALID_ARG, "negative sweep count");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < n_sweeps; ++i) MF_HIP(hipGraphLaunch(g->exec, hs));
+  for (auto* p : g->probs) p->sweep += static_cast<uint64_t>(n_sweeps);
+  return MF_OK;
+}
+
+void mf_graph_destroy(mf_graph* g) { delete g; }
 
 const char* mf_last_error(void) { return g_last_error.c_str(); }
 

@@ -49,7 +49,7 @@ struct SweepArgs {
   int32_t n_wg_x;
   int32_t staging_chain;  // chain whose state the staging buffer exchanges
   int32_t sample_pk;
-  uint32_t sweep;
+  uint32_t* ctr;          // [0] sweep index, [1] finished workgroups of the last pass
   uint32_t chain0;
   uint32_t key0, key1;
 };
@@ -178,6 +178,7 @@ zpass_kernel(SweepArgs<R> a) {
   cx<R>* spec = a.spec + static_cast<size_t>(c) * a.spec_stride;
   load_twiddles(tw, a.tw, N, NT);
   cx<R> v[EPT];
+  const uint32_t sweep = a.ctr[0];
 
   if (MODE != kZSetState) {
 #pragma unroll
@@ -229,13 +230,13 @@ zpass_kernel(SweepArgs<R> a) {
       for (int cq = 0; cq < RL / 4; ++cq) {
         R ga[4], gb[4];
         {
-          const Words4 w = philox4x32_10(wa + NSL * cq, a.sweep, kPhaseMessenger, chain,
+          const Words4 w = philox4x32_10(wa + NSL * cq, sweep, kPhaseMessenger, chain,
                                          a.key0, a.key1);
           box_muller(w.x0, w.x1, ga[0], ga[1]);
           box_muller(w.x2, w.x3, ga[2], ga[3]);
         }
         {
-          const Words4 w = philox4x32_10(wa + N / 4 + NSL * cq, a.sweep, kPhaseMessenger,
+          const Words4 w = philox4x32_10(wa + N / 4 + NSL * cq, sweep, kPhaseMessenger,
                                          chain, a.key0, a.key1);
           box_muller(w.x0, w.x1, gb[0], gb[1]);
           box_muller(w.x2, w.x3, gb[2], gb[3]);
@@ -299,23 +300,39 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
     if (tid < h) red[tid] += red[tid + h];
     __syncthreads();
   }
-  if (tid != 0) return;
-  const double m = static_cast<double>(a.m);
-  const double sigma = red[0] * m * m;
-  const double tau = a.tau[c];
-  double* pk = a.pk + static_cast<size_t>(c) * a.nb;
-  double p = pk[b];
-  if (a.sample_pk && a.counts[b] > 0.0) {
-    const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.sweep,
-                              a.chain0 + c, a.key0, a.key1);
-    p = sigma / (2.0 * m * g);
-    if (!(g > 0.0) || !isfinite(p) || !isfinite(sigma)) {
-      atomicOr(a.status + c, 1u);
-      p = pk[b];
+  if (tid == 0) {
+    const double m = static_cast<double>(a.m);
+    const double sigma = red[0] * m * m;
+    const double tau = a.tau[c];
+    double* pk = a.pk + static_cast<size_t>(c) * a.nb;
+    double p = pk[b];
+    if (a.sample_pk && a.counts[b] > 0.0) {
+      const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.ctr[0],
+                                a.chain0 + c, a.key0, a.key1);
+      p = sigma / (2.0 * m * g);
+      if (!(g > 0.0) || !isfinite(p) || !isfinite(sigma)) {
+        atomicOr(a.status + c, 1u);
+        p = pk[b];
+      }
+      pk[b] = p;
     }
-    pk[b] = p;
+    write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b, p, tau, m);
   }
-  write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b, p, tau, m);
+}
+
+// End of the last pass of a sweep: the workgroup that finishes last (of every
+// chain) advances the sweep index, after every workgroup has read it.
+template <typename R>
+__device__ __forceinline__ void sweep_done(const SweepArgs<R>& a) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t total = gridDim.x * gridDim.y * gridDim.z;
+    if (atomicAdd(a.ctr + 1, 1u) == total - 1) {
+      atomicExch(a.ctr + 1, 0u);
+      atomicAdd(a.ctr, 1u);
+    }
+  }
 }
 
 // Table from the current P of every chain (set-up and state restore).
@@ -345,6 +362,7 @@ ypass_kernel(SweepArgs<R> a) {
   if (INV) {
     if (blk < a.nb) {
       pk_draw_block<R, NT>(a, blk, blockIdx.z, reinterpret_cast<double*>(lds));
+      sweep_done(a);
       return;
     }
     blk -= a.nb;
@@ -367,6 +385,7 @@ ypass_kernel(SweepArgs<R> a) {
     TL::template out_pos<false>(tid, e, pen, n);
     base[pen * N + n] = v[e];
   }
+  if (INV) sweep_done(a);
 }
 
 // ---------------------------------------------------------------- x split
@@ -409,6 +428,7 @@ ysplit_kernel(SweepArgs<R> a) {
   if (INV) {
     if (blk < a.nb) {
       pk_draw_block<R, NT>(a, blk, blockIdx.z, reinterpret_cast<double*>(lds));
+      sweep_done(a);
       return;
     }
     blk -= a.nb;
@@ -481,6 +501,7 @@ ysplit_kernel(SweepArgs<R> a) {
       TL::template out_pos<false>(tid, e, pen, n);
       plane[static_cast<size_t>(q + 16 * pen) * N + n] = v[e];
     }
+    sweep_done(a);
   }
 }
 
@@ -504,6 +525,7 @@ struct DrawCtx {
   float qscale;
   int nb;
   uint32_t chain;
+  uint32_t sweep;
 };
 
 // Signal draw of one register slot: v[r] holds t^ of mode (ix, iy, kz) with
@@ -534,7 +556,7 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
     R g[4];
     {
       const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
-      const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
+      const Words4 w = philox4x32_10(w0, d.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
       box_muller(w.x0, w.x1, g[0], g[1]);
       box_muller(w.x2, w.x3, g[2], g[3]);
     }
@@ -571,7 +593,7 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
       const int b = bin_of(mx * mx + r2, d.qthr, d.nb, d.qscale);
       const cx<R> ab = d.tab[b];
       const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px & (H - 1)));
-      const Words4 w = philox4x32_10(w0, a.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
+      const Words4 w = philox4x32_10(w0, d.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
       R g0, g1;
       if (px >= H) box_muller(w.x2, w.x3, g0, g1);
       else box_muller(w.x0, w.x1, g0, g1);
@@ -603,6 +625,7 @@ __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c
   d.qscale = static_cast<float>(4.0 * nb * nb / (3.0 * n * n));
   d.nb = nb;
   d.chain = a.chain0 + c;
+  d.sweep = a.ctr[0];
   return d;
 }
 

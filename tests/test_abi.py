@@ -1,0 +1,118 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/mf.h declares (and the binding declares the same set), and host-side
+validation rejects bad descriptors and inputs with the documented status
+before touching a device."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1402_1763_amd import binding, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(binding.SIGNATURES), set(names) ^ set(binding.SIGNATURES)
+
+
+def test_supported_sizes(lib):
+    assert [n for n in range(4, 1100) if binding.mf_supported_n(n)] == [8, 16, 32, 64, 128, 256, 512]
+
+
+def test_workspace_bytes_and_descriptor_errors(lib):
+    d = binding.make_desc(256, 64, 2000.0, 1, "fp32")
+    ws = binding.mf_workspace_bytes(d)
+    m = 256 ** 3
+    assert 16 * m < ws < 16.2 * m      # FP32: coef 8 B, spectrum 4.03 B, staging 4 B per voxel
+    d64 = binding.make_desc(256, 64, 2000.0, 1, "fp64")
+    assert binding.mf_workspace_bytes(d64) > 1.9 * ws
+    bad = [binding.make_desc(48, 16, 500.0, 1), binding.make_desc(32, 0, 500.0, 1),
+           binding.make_desc(32, 16, -1.0, 1), binding.make_desc(32, 16, 500.0, 1, n_chains=0)]
+    codes = []
+    for desc in bad:
+        with pytest.raises(binding.MFError) as e:
+            binding.mf_workspace_bytes(desc)
+        codes.append(e.value.status)
+    assert codes == [binding.MF_E_UNSUPPORTED_SIZE, binding.MF_E_INVALID_ARG,
+                     binding.MF_E_INVALID_ARG, binding.MF_E_INVALID_ARG]
+    d.precision = 7
+    with pytest.raises(binding.MFError):
+        binding.mf_workspace_bytes(d)
+
+
+def _init(desc, data, noise, pk, ws_ptr=256, ws_bytes=1 << 40):
+    return binding.mf_init_problem(desc, [data], [noise], [pk], None, ws_ptr, ws_bytes, stream=0)
+
+
+def test_init_validation_happens_on_the_host(lib):
+    w = workloads.small_workload(8, 4)
+    pb = workloads.make_problem(w)
+    desc = binding.make_desc(8, 4, w.box, 1, "fp64")
+    # tau above the smallest observed noise variance violates N - T > 0
+    tmin = pb["noise_var"][np.isfinite(pb["noise_var"])].min()
+    desc.tau = tmin * 1.01
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], pb["noise_var"], pb["pk_init"])
+    assert e.value.status == binding.MF_E_TAU
+    desc.tau = 0.0
+    noise = pb["noise_var"].copy()
+    noise[1, 2, 3] = np.nan
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], noise, pb["pk_init"])
+    assert e.value.status == binding.MF_E_NONFINITE
+    noise = pb["noise_var"].copy()
+    noise[0, 0, 0] = -1.0
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], noise, pb["pk_init"])
+    assert e.value.status == binding.MF_E_NONFINITE
+    data = pb["data"].copy()
+    obs = np.argwhere(np.isfinite(pb["noise_var"]))[0]
+    data[tuple(obs)] = np.inf
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, data, pb["noise_var"], pb["pk_init"])
+    assert e.value.status == binding.MF_E_NONFINITE
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], np.full_like(noise, np.inf), pb["pk_init"])
+    assert e.value.status == binding.MF_E_INVALID_ARG        # nothing observed
+    pk = pb["pk_init"].copy()
+    pk[2] = -1.0
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], pb["noise_var"], pk)
+    assert e.value.status == binding.MF_E_NONFINITE
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], pb["noise_var"], pb["pk_init"], ws_ptr=0)
+    assert e.value.status == binding.MF_E_WORKSPACE
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], pb["noise_var"], pb["pk_init"], ws_ptr=256 + 8)
+    assert e.value.status == binding.MF_E_WORKSPACE
+    with pytest.raises(binding.MFError) as e:
+        _init(desc, pb["data"], pb["noise_var"], pb["pk_init"], ws_bytes=1024)
+    assert e.value.status == binding.MF_E_WORKSPACE
+    assert "workspace" in binding.mf_last_error()
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.mf_gibbs_sweep(None, 1, None) == binding.MF_E_INVALID_ARG
+    assert lib.mf_get_chain_state(None, 0, None, None, None, None) == binding.MF_E_INVALID_ARG
+    assert lib.mf_graph_launch(None, 1, None) == binding.MF_E_INVALID_ARG
+    lib.mf_destroy_problem(None)
+    lib.mf_graph_destroy(None)
