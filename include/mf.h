@@ -65,7 +65,7 @@ typedef enum {
 } mf_precision;
 
 typedef struct {
-  int32_t n;          /* grid side N: a power of two, 8 <= N <= 512 */
+  int32_t n;          /* grid side N: 8, 16, 32, 48, 64, 80, 96, 128, 256 or 512 */
   int32_t n_bins;     /* number of |k| bins, 1 <= n_bins <= 1024 */
   double box;         /* box side L (> 0) */
   double tau;         /* messenger variance; <= 0 selects min observed N_i */

@@ -81,10 +81,11 @@ __host__ __device__ constexpr int bitrev(int i, int bits) {
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// In-register DFT of size RAD (2..16) on v[0 .. RAD), natural order in and
-// out: radix-2 decimation in frequency, then a bit-reversal permutation.
+// In-register DFT of a power-of-two size RAD (2..16) on v[0 .. RAD), natural
+// order in and out: radix-2 decimation in frequency, then a bit-reversal
+// permutation.
 template <typename R, int RAD, bool INV>
-__device__ __forceinline__ void dft(cx<R>* v) {
+__device__ __forceinline__ void dft_pow2(cx<R>* v) {
 #pragma unroll
   for (int len = RAD; len >= 2; len >>= 1) {
     const int half = len / 2;
@@ -106,6 +107,74 @@ __device__ __forceinline__ void dft(cx<R>* v) {
   for (int i = 0; i < RAD; ++i) v[i] = t[i];
 }
 
+// -i z (forward) or +i z (inverse)
+template <typename R, bool INV>
+__device__ __forceinline__ cx<R> mul_mi(cx<R> z) {
+  return INV ? cx<R>{-z.y, z.x} : cx<R>{z.y, -z.x};
+}
+
+// 3-point DFT: X0 = a + (b + c), X1,2 = a - (b + c)/2 -+ i sin(2pi/3) (b - c).
+template <typename R, bool INV>
+__device__ __forceinline__ void dft3(cx<R>* v) {
+  const R s3 = R(0.86602540378443864676);
+  const cx<R> a = v[0], b = v[1], c = v[2];
+  const cx<R> t1{b.x + c.x, b.y + c.y};
+  const cx<R> t2{a.x - R(0.5) * t1.x, a.y - R(0.5) * t1.y};
+  const cx<R> d = mul_mi<R, INV>(cx<R>{s3 * (b.x - c.x), s3 * (b.y - c.y)});
+  v[0] = cx<R>{a.x + t1.x, a.y + t1.y};
+  v[1] = cx<R>{t2.x + d.x, t2.y + d.y};
+  v[2] = cx<R>{t2.x - d.x, t2.y - d.y};
+}
+
+// 5-point DFT from the symmetric / antisymmetric pairs (a1 +- a4, a2 +- a3)
+// with c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5).
+template <typename R, bool INV>
+__device__ __forceinline__ void dft5(cx<R>* v) {
+  const R c1 = R(0.30901699437494742410), c2 = R(-0.80901699437494742410);
+  const R s1 = R(0.95105651629515357212), s2 = R(0.58778525229247312917);
+  const cx<R> a0 = v[0];
+  const cx<R> p1{v[1].x + v[4].x, v[1].y + v[4].y}, m1{v[1].x - v[4].x, v[1].y - v[4].y};
+  const cx<R> p2{v[2].x + v[3].x, v[2].y + v[3].y}, m2{v[2].x - v[3].x, v[2].y - v[3].y};
+  const cx<R> e1{a0.x + c1 * p1.x + c2 * p2.x, a0.y + c1 * p1.y + c2 * p2.y};
+  const cx<R> e2{a0.x + c2 * p1.x + c1 * p2.x, a0.y + c2 * p1.y + c1 * p2.y};
+  const cx<R> o1 = mul_mi<R, INV>(cx<R>{s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y});
+  const cx<R> o2 = mul_mi<R, INV>(cx<R>{s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y});
+  v[0] = cx<R>{a0.x + p1.x + p2.x, a0.y + p1.y + p2.y};
+  v[1] = cx<R>{e1.x + o1.x, e1.y + o1.y};
+  v[4] = cx<R>{e1.x - o1.x, e1.y - o1.y};
+  v[2] = cx<R>{e2.x + o2.x, e2.y + o2.y};
+  v[3] = cx<R>{e2.x - o2.x, e2.y - o2.y};
+}
+
+// 6-point DFT: two 3-point DFTs of the even and odd samples, combined with
+// w6^k = exp(-+ i pi k / 3): X_k = E_k + w6^k O_k, X_{k+3} = E_k - w6^k O_k.
+template <typename R, bool INV>
+__device__ __forceinline__ void dft6(cx<R>* v) {
+  cx<R> e[3] = {v[0], v[2], v[4]}, o[3] = {v[1], v[3], v[5]};
+  dft3<R, INV>(e);
+  dft3<R, INV>(o);
+  const R h = R(0.5), s3 = R(0.86602540378443864676);
+  const cx<R> w1 = INV ? cx<R>{h, s3} : cx<R>{h, -s3};
+  const cx<R> w2 = INV ? cx<R>{-h, s3} : cx<R>{-h, -s3};
+  const cx<R> t0 = o[0], t1 = cmul(o[1], w1), t2 = cmul(o[2], w2);
+  v[0] = cx<R>{e[0].x + t0.x, e[0].y + t0.y};
+  v[3] = cx<R>{e[0].x - t0.x, e[0].y - t0.y};
+  v[1] = cx<R>{e[1].x + t1.x, e[1].y + t1.y};
+  v[4] = cx<R>{e[1].x - t1.x, e[1].y - t1.y};
+  v[2] = cx<R>{e[2].x + t2.x, e[2].y + t2.y};
+  v[5] = cx<R>{e[2].x - t2.x, e[2].y - t2.y};
+}
+
+// In-register DFT of size RAD (1, 2, 3, 4, 5, 6, 8, 16), natural order.
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void dft(cx<R>* v) {
+  if constexpr (RAD == 1) return;
+  else if constexpr (RAD == 3) dft3<R, INV>(v);
+  else if constexpr (RAD == 5) dft5<R, INV>(v);
+  else if constexpr (RAD == 6) dft6<R, INV>(v);
+  else dft_pow2<R, RAD, INV>(v);
+}
+
 // Radix schedule per size (normal order); the reversed order runs it backwards.
 template <int N>
 struct Radices;
@@ -116,6 +185,23 @@ template <> struct Radices<64> { static constexpr int n = 2; static constexpr in
 template <> struct Radices<128> { static constexpr int n = 2; static constexpr int r[3] = {16, 8, 1}; };
 template <> struct Radices<256> { static constexpr int n = 2; static constexpr int r[3] = {16, 16, 1}; };
 template <> struct Radices<512> { static constexpr int n = 3; static constexpr int r[3] = {8, 8, 8}; };
+template <> struct Radices<48> { static constexpr int n = 3; static constexpr int r[3] = {3, 4, 4}; };
+template <> struct Radices<80> { static constexpr int n = 3; static constexpr int r[3] = {5, 4, 4}; };
+template <> struct Radices<96> { static constexpr int n = 3; static constexpr int r[3] = {3, 4, 8}; };
+
+__host__ __device__ constexpr int gcd_(int a, int b) { return b == 0 ? a : gcd_(b, a % b); }
+
+// Elements per thread of a size-N pencil tile: 16, or the least common
+// multiple of the radices for mixed-radix sizes.
+template <int N>
+__host__ __device__ constexpr int ept() {
+  int l = 1;
+  for (int i = 0; i < Radices<N>::n; ++i) l = l / gcd_(l, Radices<N>::r[i]) * Radices<N>::r[i];
+  return (16 % l == 0) ? 16 : l;
+}
+
+template <int N>
+__host__ __device__ constexpr bool pow2() { return (N & (N - 1)) == 0; }
 
 template <int N, bool REV>
 __host__ __device__ constexpr int radix_at(int s) {

@@ -41,7 +41,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool supported(int n) {
-  return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512;
+  return n == 8 || n == 16 || n == 32 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 ||
+         n == 256 || n == 512;
 }
 
 template <typename R, int N>
@@ -62,7 +63,8 @@ Shape shape_of(int n) {
   switch (n) {
 #define MF_SHAPE(NN) \
   case NN: return Shape{Geometry<R, NN>::xp};
-    MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(64) MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
+    MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(48) MF_SHAPE(64) MF_SHAPE(80) MF_SHAPE(96)
+    MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
 #undef MF_SHAPE
   }
   return Shape{0};
@@ -108,7 +110,7 @@ Layout make_layout(const mf_chain_desc& d) {
 mf_status check_desc(const mf_chain_desc* d) {
   if (!d) return fail(MF_E_INVALID_ARG, "descriptor is NULL");
   if (!supported(d->n))
-    return fail(MF_E_UNSUPPORTED_SIZE, "grid side %d unsupported (power of two in [8, 512])", d->n);
+    return fail(MF_E_UNSUPPORTED_SIZE, "grid side %d unsupported (8, 16, 32, 48, 64, 80, 96, 128, 256 or 512)", d->n);
   if (d->n_bins < 1 || d->n_bins > 1024)
     return fail(MF_E_INVALID_ARG, "n_bins %d outside [1, 1024]", d->n_bins);
   if (!(d->box > 0.0) || !std::isfinite(d->box))
@@ -271,7 +273,10 @@ void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st) {
     case 8: launch_n<R, 8>(id, a, nch, st); break;
     case 16: launch_n<R, 16>(id, a, nch, st); break;
     case 32: launch_n<R, 32>(id, a, nch, st); break;
+    case 48: launch_n<R, 48>(id, a, nch, st); break;
     case 64: launch_n<R, 64>(id, a, nch, st); break;
+    case 80: launch_n<R, 80>(id, a, nch, st); break;
+    case 96: launch_n<R, 96>(id, a, nch, st); break;
     case 128: launch_n<R, 128>(id, a, nch, st); break;
     case 256: launch_n<R, 256>(id, a, nch, st); break;
     case 512: launch_n<R, 512>(id, a, nch, st); break;
@@ -361,7 +366,10 @@ mf_status upload_coef(mf_problem* p, int c, const double* data, const double* no
     case 8: permute_coef<R, 8>(buf, data, noise_var, tau); break;
     case 16: permute_coef<R, 16>(buf, data, noise_var, tau); break;
     case 32: permute_coef<R, 32>(buf, data, noise_var, tau); break;
+    case 48: permute_coef<R, 48>(buf, data, noise_var, tau); break;
     case 64: permute_coef<R, 64>(buf, data, noise_var, tau); break;
+    case 80: permute_coef<R, 80>(buf, data, noise_var, tau); break;
+    case 96: permute_coef<R, 96>(buf, data, noise_var, tau); break;
     case 128: permute_coef<R, 128>(buf, data, noise_var, tau); break;
     case 256: permute_coef<R, 256>(buf, data, noise_var, tau); break;
     case 512: permute_coef<R, 512>(buf, data, noise_var, tau); break;

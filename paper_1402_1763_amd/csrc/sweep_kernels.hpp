@@ -60,8 +60,8 @@ enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2 };
 // z-pass: one ix, P consecutive iy (NPAIR complex pencils), pencil-fastest.
 template <typename R, int N>
 struct ZTile {
-  static constexpr int EPT = 16;
-  static constexpr int P = N >= 32 ? (sizeof(R) == 4 ? 32 : 16) : N;
+  static constexpr int EPT = ept<N>();
+  static constexpr int P = N >= 32 ? ((sizeof(R) == 4 && N % 32 == 0) ? 32 : 16) : N;
   static constexpr int NPAIR = P / 2;
   static constexpr int NT = NPAIR * N / EPT;
   static constexpr int PSTR = N + 1;
@@ -267,7 +267,7 @@ zpass_kernel(SweepArgs<R> a) {
   for (int it = tid; it < (H + 1) * NPAIR; it += NT) {
     const int k = it / NPAIR, p = it % NPAIR;
     const cx<R> u = lds[TL::lidx(p, k)];
-    const cx<R> w = lds[TL::lidx(p, (N - k) & (N - 1))];
+    const cx<R> w = lds[TL::lidx(p, (N - k) % N)];
     const cx<R> A{R(0.5) * (u.x + w.x), R(0.5) * (u.y - w.y)};
     const cx<R> B{R(0.5) * (u.y + w.y), R(0.5) * (w.x - u.x)};
     st2(spec + (static_cast<size_t>(k) * N + ix) * N + iy0 + 2 * p, A, B);
@@ -283,8 +283,7 @@ __device__ __forceinline__ void write_table(R* tab, int b, double p, double tau,
   tab[2 * b + 1] = static_cast<R>(sqrt(tau * f / (2.0 * m)));
 }
 
-// P(k) step of bin b of chain c by one workgroup of NTH threads (a power of
-// two): sums the x-pass partials in a fixed order (strided per thread, then a
+// P(k) step of bin b of chain c by one workgroup of NTH threads: sums the x-pass partials in a fixed order (strided per thread, then a
 // tree in `red`, NTH doubles), forms sigma_b = M^2 sum w |s^/M|^2 and draws
 // P_b = sigma_b / (2 M g), g ~ Gamma(n_b / 2, 1) -- the inverse-gamma
 // conditional of P_b under Jeffreys' prior -- then refreshes (A_b, B_b).
@@ -296,7 +295,13 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
   for (int w = tid; w < a.n_wg_x; w += NTH) s += part[w];
   red[tid] = s;
   __syncthreads();
-  for (int h = NTH / 2; h > 0; h >>= 1) {
+  // fixed-order tree: fold onto the largest power of two <= NTH, then halve
+  constexpr int P2 = 1 << ilog2(NTH);
+  if (P2 < NTH) {
+    if (tid < NTH - P2) red[tid] += red[tid + P2];
+    __syncthreads();
+  }
+  for (int h = P2 / 2; h > 0; h >>= 1) {
     if (tid < h) red[tid] += red[tid + h];
     __syncthreads();
   }
@@ -407,10 +412,10 @@ __host__ __device__ constexpr bool split_x() { return N >= 32 && N <= 256; }
 template <typename R, int N>
 struct YSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
-  static constexpr int EPT = 16;
+  static constexpr int EPT = ept<N>();
   static constexpr int NT = NA * N / EPT;
-  static constexpr int COLS = 16 / NA;     // columns per thread in the x-stage layout
-  static constexpr int PADS = ilog2(Radices<N>::r[0]);
+  static constexpr int COLS = EPT / NA;    // columns per thread in the x-stage layout
+  static constexpr int PADS = pow2<Radices<N>::r[0]>() ? ilog2(Radices<N>::r[0]) : 2;
   static constexpr int PSTR = N + (N >> PADS);
   using TL = Tile<N, NA, NT, false, PSTR, PADS>;
 };
@@ -549,7 +554,7 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
   const double wgt = herm ? 1.0 : 2.0;
   const int my = wavenumber(iy, N);
   const int r2 = my * my + kz * kz;
-  const int py = (N - iy) & (N - 1);
+  const int py = (N - iy) % N;
 #pragma unroll
   for (int r = 0; r < RL / 2; ++r) {
     const int ixl = q + S * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
@@ -566,7 +571,7 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
       const int x = ixl + h * H;
       const int mx = wavenumber(x, N);
       const int qq = mx * mx + r2;
-      const int plin = ((N - x) & (N - 1)) * N + py, lin = x * N + iy;
+      const int plin = ((N - x) % N) * N + py, lin = x * N + iy;
       if (herm && plin < lin) continue;   // drawn in the second loop
       cx<R> out{R(0), R(0)};
       if (qq > 0) {
@@ -587,12 +592,12 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
       const int x = q + S * e;
-      const int px = (N - x) & (N - 1);
+      const int px = (N - x) % N;
       if (px * N + py >= x * N + iy) continue;
       const int mx = wavenumber(x, N);
       const int b = bin_of(mx * mx + r2, d.qthr, d.nb, d.qscale);
       const cx<R> ab = d.tab[b];
-      const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px & (H - 1)));
+      const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px % H));
       const Words4 w = philox4x32_10(w0, d.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
       R g0, g1;
       if (px >= H) box_muller(w.x2, w.x3, g0, g1);
@@ -665,7 +670,11 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
 template <typename R, int N>
 struct XSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
-  static constexpr int P = (256 / NA) > N ? N : 256 / NA;   // columns per workgroup
+  // columns per workgroup: the largest power of two <= 256 / NA dividing N
+  static constexpr int P = (256 / NA >= 256 && N % 256 == 0) ? 256
+                           : (256 / NA >= 128 && N % 128 == 0) ? 128
+                           : (256 / NA >= 64 && N % 64 == 0)   ? 64
+                           : (256 / NA >= 32 && N % 32 == 0)   ? 32 : 16;
   static constexpr int NT = P * NA;
   static constexpr int HG = 2;
   static constexpr int NHIST = ((NT + 63) / 64) * HG;

@@ -35,7 +35,7 @@ def test_exports_every_declared_function(lib):
 
 
 def test_supported_sizes(lib):
-    assert [n for n in range(4, 1100) if binding.mf_supported_n(n)] == [8, 16, 32, 64, 128, 256, 512]
+    assert [n for n in range(4, 1100) if binding.mf_supported_n(n)] == [8, 16, 32, 48, 64, 80, 96, 128, 256, 512]
 
 
 def test_workspace_bytes_and_descriptor_errors(lib):
@@ -45,7 +45,7 @@ def test_workspace_bytes_and_descriptor_errors(lib):
     assert 16 * m < ws < 16.2 * m      # FP32: coef 8 B, spectrum 4.03 B, staging 4 B per voxel
     d64 = binding.make_desc(256, 64, 2000.0, 1, "fp64")
     assert binding.mf_workspace_bytes(d64) > 1.9 * ws
-    bad = [binding.make_desc(48, 16, 500.0, 1), binding.make_desc(32, 0, 500.0, 1),
+    bad = [binding.make_desc(40, 16, 500.0, 1), binding.make_desc(32, 0, 500.0, 1),
            binding.make_desc(32, 16, -1.0, 1), binding.make_desc(32, 16, 500.0, 1, n_chains=0)]
     codes = []
     for desc in bad:

@@ -87,3 +87,24 @@ def test_benchmark_problem_sweep_from_gpu_state():
     print(f"  sweep 31 from GPU state: err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
     assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
     assert np.all(np.isfinite(p31)) and np.all(p31 > 0)
+
+
+@pytest.mark.timeout(600)
+def test_largest_grid_one_sweep():
+    """512^3 (three-stage transforms, whole-transform x-pass): one sweep from a
+    random initial field against one oracle sweep."""
+    w = workloads.Workload("test-512^3", n=512, box=4000.0, n_bins=32, mask="random",
+                           mask_frac=0.2, precision="fp32", seed=5, rng_seed=9)
+    pb = workloads.make_problem(w)
+    s0 = np.random.default_rng(6).standard_normal((w.n,) * 3) * 3.0
+    print("512^3: GPU sweep", flush=True)
+    g = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                        seed=w.rng_seed, precision=w.precision, s_init=s0)
+    g.sweep(1)
+    s_gpu, p_gpu, done = g.state()
+    g.close()
+    print("512^3: oracle sweep", flush=True)
+    s_ref, p_ref = run_oracle(w, pb, 1, s0=s0)
+    err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+    print(f"  err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
+    assert done == 1 and err_s < TOL["fp32"] and err_p < TOL["fp32"]

@@ -113,3 +113,12 @@ def test_deterministic_repeat():
         g.close()
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("n,precision", [(48, "fp64"), (80, "fp64"), (96, "fp64"),
+                                         (48, "fp32"), (80, "fp32"), (96, "fp32")])
+def test_parity_mixed_radix_sizes(n, precision):
+    """Grid sides with radix-3 and radix-5 factors (48 = 3 * 16, 80 = 5 * 16,
+    96 = 6 * 16): random masks with 10-40% unobserved voxels."""
+    err_s, err_p = _case(n, 16, precision, "random", 10, seed=n, mask_frac=0.1 + 0.3 * (n % 7) / 7)
+    assert err_s < TOL[precision] and err_p < TOL[precision]
