@@ -225,7 +225,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
   using YS = mf::YSTile<R, N>;
   using XS = mf::XSTile<R, N>;
   constexpr bool split = mf::split_x<N>();
-  const dim3 zgrid(N / ZT::P, N, nch), zgrid1(N / ZT::P, N, 1);
+  const dim3 zgrid(N / ZT::P, N / ZT::IXB, nch), zgrid1(N / ZT::P, N / ZT::IXB, 1);
   const size_t tables = 2 * a.nb * sizeof(R) + a.nb * 4;
   switch (id) {
     case kZ:
@@ -239,7 +239,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       break;
     case kYF:
       if constexpr (split)
-        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 * (N / 2 + 1), 1, nch),
+        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 / YS::G * (N / 2 + 1), 1, nch),
                            dim3(YS::NT), 0, st, a);
       else
         hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), dim3((N / 2 + 1) * N / YT::NPEN, 1, nch),
@@ -247,7 +247,8 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       break;
     case kYI:
       if constexpr (split)
-        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, true>), dim3(16 * (N / 2 + 1) + a.nb, 1, nch),
+        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, true>),
+                           dim3(16 / YS::G * (N / 2 + 1) + a.nb, 1, nch),
                            dim3(YS::NT), 0, st, a);
       else
         hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>),
@@ -299,10 +300,10 @@ mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t s
   return MF_OK;
 }
 
-// Device sweep counter := sweep (the sweep kernels read it; the last pass of
-// every sweep advances it).
+// Device sweep counter := sweep in both slots (the z-pass reads slot 0, the
+// x-pass and the P draw slot 1; the forward y-pass advances slot 0).
 mf_status write_counter(mf_problem* p, uint64_t sweep, hipStream_t st) {
-  const uint32_t c[2] = {static_cast<uint32_t>(sweep), 0u};
+  const uint32_t c[2] = {static_cast<uint32_t>(sweep), static_cast<uint32_t>(sweep)};
   MF_HIP(hipMemcpyAsync(p->ws + p->L.ctr, c, sizeof(c), hipMemcpyHostToDevice, st));
   MF_HIP(hipStreamSynchronize(st));
   return MF_OK;
@@ -340,7 +341,7 @@ mf_status download_real(mf_problem* p, double* dst, const void* src, size_t coun
 template <typename R, int N>
 void permute_coef(std::vector<R>& out, const double* data, const double* noise_var, double tau) {
   using T = mf::ZTile<R, N>;
-  const int tiles = N * (N / T::P);
+  const int tiles = (N / T::IXB) * (N / T::P);
   out.assign(static_cast<size_t>(2) * N * N * N, R(0));
   auto alpha = [&](size_t i) { return std::isinf(noise_var[i]) ? 1.0 : 1.0 - tau / noise_var[i]; };
   auto beta = [&](size_t i) { return std::isinf(noise_var[i]) ? 0.0 : tau * data[i] / noise_var[i]; };

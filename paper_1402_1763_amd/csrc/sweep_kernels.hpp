@@ -49,7 +49,7 @@ struct SweepArgs {
   int32_t n_wg_x;
   int32_t staging_chain;  // chain whose state the staging buffer exchanges
   int32_t sample_pk;
-  uint32_t* ctr;          // [0] sweep index, [1] finished workgroups of the last pass
+  uint32_t* ctr;          // [0] next sweep's index, [1] index of the sweep in flight
   uint32_t chain0;
   uint32_t key0, key1;
 };
@@ -57,15 +57,36 @@ struct SweepArgs {
 enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2 };
 
 // ---------------------------------------------------------------- tiles
-// z-pass: one ix, P consecutive iy (NPAIR complex pencils), pencil-fastest.
+// Largest power of two d <= cap that divides n (at least 1).
+__host__ __device__ constexpr int pow2_divisor(int n, int cap) {
+  int d = 1;
+  while (d * 2 <= cap && n % (d * 2) == 0) d *= 2;
+  return d;
+}
+
+// Largest divisor d of n with d <= cap (at least 1).
+__host__ __device__ constexpr int divisor_below(int n, int cap) {
+  int d = 1;
+  for (int k = 1; k <= n && k <= cap; ++k)
+    if (n % k == 0) d = k;
+  return d;
+}
+
+// z-pass: IXB consecutive ix and P consecutive iy (NPAIR complex pencils per
+// ix), pencil-fastest; pencil pen = ixb * NPAIR + p.  Small grids take several
+// ix per workgroup, up to 256 threads and 40 KB of staging LDS.
 template <typename R, int N>
 struct ZTile {
   static constexpr int EPT = ept<N>();
   static constexpr int P = N >= 32 ? ((sizeof(R) == 4 && N % 32 == 0) ? 32 : 16) : N;
   static constexpr int NPAIR = P / 2;
-  static constexpr int NT = NPAIR * N / EPT;
+  static constexpr int IXCAP_T = 256 / (NPAIR * N / EPT);
+  static constexpr int IXCAP_L = 40960 / (NPAIR * (N + 1) * 2 * static_cast<int>(sizeof(R)));
+  static constexpr int IXB = pow2_divisor(N, IXCAP_T < IXCAP_L ? IXCAP_T : IXCAP_L);
+  static constexpr int NPEN = IXB * NPAIR;
+  static constexpr int NT = NPEN * N / EPT;
   static constexpr int PSTR = N + 1;
-  using TL = Tile<N, NPAIR, NT, true, PSTR, 0>;
+  using TL = Tile<N, NPEN, NT, true, PSTR, 0>;
 };
 
 // y-pass: NPEN consecutive contiguous pencils, q-fastest, padded LDS.
@@ -131,22 +152,22 @@ __device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
 // ---------------------------------------------------------------- z-pass
 // Messenger coefficients are stored in the z-pass's thread order so that each
 // lane's loads are contiguous: entry ((tile * EPT + e) * NT + tid) holds
-// (alpha_a, alpha_b, beta_a, beta_b) of the voxels (ix, iy0 + 2p (+1), n)
-// that thread tid holds as element e after the inverse z-DFT, where
-// tile = ix * (N / P) + iy0 / P.  alpha = 1 - tau/N_i, beta = tau d_i / N_i
-// on observed voxels and (1, 0) elsewhere.
+// (alpha_a, alpha_b, beta_a, beta_b) of the voxels (ix, iya (+1), n) that
+// thread tid holds as element e after the inverse z-DFT, where
+// tile = (ix0 / IXB) * (N / P) + iy0 / P.  alpha = 1 - tau/N_i,
+// beta = tau d_i / N_i on observed voxels and (1, 0) elsewhere.
 template <typename R, int N>
 __host__ __device__ inline void zpass_coef_voxel(int tile, int e, int tid, int& ix, int& iya,
                                                  int& n) {
   using T = ZTile<R, N>;
-  int p = 0;
-  T::TL::template out_pos<false>(tid, e, p, n);
-  ix = tile / (N / T::P);
-  iya = (tile % (N / T::P)) * T::P + 2 * p;
+  int pen = 0;
+  T::TL::template out_pos<false>(tid, e, pen, n);
+  ix = (tile / (N / T::P)) * T::IXB + pen / T::NPAIR;
+  iya = (tile % (N / T::P)) * T::P + 2 * (pen % T::NPAIR);
 }
 
-// Workgroup = one ix and P consecutive iy; z pencils (iy, iy + 1) are packed
-// as one complex pencil a + i b.
+// Workgroup = IXB consecutive ix and P consecutive iy; z pencils (iy, iy + 1)
+// are packed as one complex pencil a + i b.
 //   load    : Z_k = A_k + i B_k from the half spectra, Hermitian-extended
 //             (A_{N-k} = conj A_k; imaginary parts of kz = 0, N/2 dropped),
 //             straight into the registers of the first inverse stage
@@ -165,29 +186,35 @@ __global__ void __launch_bounds__((ZTile<R, N>::NT))
 zpass_kernel(SweepArgs<R> a) {
   using T = ZTile<R, N>;
   using TL = typename T::TL;
-  constexpr int NPAIR = T::NPAIR, NT = T::NT, EPT = T::EPT, H = N / 2;
+  constexpr int NPAIR = T::NPAIR, NPEN = T::NPEN, NT = T::NT, EPT = T::EPT, H = N / 2;
   constexpr int RL = radix_at<N, false>(Radices<N>::n - 1);
   constexpr int NSL = N / RL;
-  __shared__ cx<R> lds[NPAIR * T::PSTR];
+  __shared__ cx<R> lds[NPEN * T::PSTR];
   __shared__ cx<R> tw[N];
   const int tid = threadIdx.x;
   const int blk = blockIdx.x;
   const int iy0 = blk * T::P;
-  const int ix = blockIdx.y;
+  const int ix0 = blockIdx.y * T::IXB;
   const int c = (MODE == kZSweep) ? static_cast<int>(blockIdx.z) : a.staging_chain;
   cx<R>* spec = a.spec + static_cast<size_t>(c) * a.spec_stride;
   load_twiddles(tw, a.tw, N, NT);
   cx<R> v[EPT];
   const uint32_t sweep = a.ctr[0];
+  // Publish this sweep's index to the later passes (the forward y-pass then
+  // advances slot 0 for the next sweep): no other z-pass workgroup reads
+  // slot 1, and the later passes start after this kernel has finished.
+  if (MODE == kZSweep && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+    a.ctr[1] = sweep;
 
   if (MODE != kZSetState) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      int p = 0, k = 0;
-      TL::template in_pos<false>(tid, e, p, k);
+      int pen = 0, k = 0;
+      TL::template in_pos<false>(tid, e, pen, k);
       const int kk = k <= H ? k : N - k;
       cx<R> A, B;
-      ld2(spec + (static_cast<size_t>(kk) * N + ix) * N + iy0 + 2 * p, A, B);
+      ld2(spec + (static_cast<size_t>(kk) * N + ix0 + pen / NPAIR) * N + iy0 + 2 * (pen % NPAIR),
+          A, B);
       if (k == 0 || k == H) v[e] = cx<R>{A.x, B.x};
       else if (k < H) v[e] = cx<R>{A.x - B.y, A.y + B.x};
       else v[e] = cx<R>{A.x + B.y, B.x - A.y};
@@ -196,9 +223,10 @@ zpass_kernel(SweepArgs<R> a) {
     if (MODE == kZGetState) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        int p = 0, n = 0;
-        TL::template out_pos<false>(tid, e, p, n);
-        const size_t ra = (static_cast<size_t>(ix) * N + iy0 + 2 * p) * N + n;
+        int pen = 0, n = 0;
+        TL::template out_pos<false>(tid, e, pen, n);
+        const size_t ra =
+            (static_cast<size_t>(ix0 + pen / NPAIR) * N + iy0 + 2 * (pen % NPAIR)) * N + n;
         a.staging[ra] = v[e].x;
         a.staging[ra + N] = v[e].y;
       }
@@ -211,21 +239,23 @@ zpass_kernel(SweepArgs<R> a) {
     constexpr R inv_n = R(1) / R(N);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      int p = 0, n = 0;
-      TL::template out_pos<false>(tid, e, p, n);
-      const size_t ra = (static_cast<size_t>(ix) * N + iy0 + 2 * p) * N + n;
+      int pen = 0, n = 0;
+      TL::template out_pos<false>(tid, e, pen, n);
+      const size_t ra =
+          (static_cast<size_t>(ix0 + pen / NPAIR) * N + iy0 + 2 * (pen % NPAIR)) * N + n;
       v[e] = cx<R>{a.staging[ra] * inv_n, a.staging[ra + N] * inv_n};
     }
   } else {
     const R tau = static_cast<R>(a.tau[c]);
     const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m +
-                    static_cast<size_t>(ix * (N / T::P) + blk) * EPT * NT * 4;
+                    static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 4;
     const uint32_t chain = a.chain0 + c;
 #pragma unroll
     for (int i = 0; i < EPT / RL; ++i) {
-      int p = 0, q = 0;
-      TL::split(tid + i * NT, NSL, p, q);
-      const uint32_t wa = static_cast<uint32_t>((ix * N + iy0 + 2 * p) * (N / 4) + q);
+      int pen = 0, q = 0;
+      TL::split(tid + i * NT, NSL, pen, q);
+      const int ix = ix0 + pen / NPAIR, iya = iy0 + 2 * (pen % NPAIR);
+      const uint32_t wa = static_cast<uint32_t>((ix * N + iya) * (N / 4) + q);
 #pragma unroll
       for (int cq = 0; cq < RL / 4; ++cq) {
         R ga[4], gb[4];
@@ -264,13 +294,13 @@ zpass_kernel(SweepArgs<R> a) {
     lds[TL::lidx(p, k)] = v[e];
   }
   __syncthreads();
-  for (int it = tid; it < (H + 1) * NPAIR; it += NT) {
-    const int k = it / NPAIR, p = it % NPAIR;
-    const cx<R> u = lds[TL::lidx(p, k)];
-    const cx<R> w = lds[TL::lidx(p, (N - k) % N)];
+  for (int it = tid; it < (H + 1) * NPEN; it += NT) {
+    const int k = it / NPEN, pen = it % NPEN;
+    const cx<R> u = lds[TL::lidx(pen, k)];
+    const cx<R> w = lds[TL::lidx(pen, (N - k) % N)];
     const cx<R> A{R(0.5) * (u.x + w.x), R(0.5) * (u.y - w.y)};
     const cx<R> B{R(0.5) * (u.y + w.y), R(0.5) * (w.x - u.x)};
-    st2(spec + (static_cast<size_t>(k) * N + ix) * N + iy0 + 2 * p, A, B);
+    st2(spec + (static_cast<size_t>(k) * N + ix0 + pen / NPAIR) * N + iy0 + 2 * (pen % NPAIR), A, B);
   }
 }
 
@@ -312,7 +342,7 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
     double* pk = a.pk + static_cast<size_t>(c) * a.nb;
     double p = pk[b];
     if (a.sample_pk && a.counts[b] > 0.0) {
-      const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.ctr[0],
+      const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.ctr[1],
                                 a.chain0 + c, a.key0, a.key1);
       p = sigma / (2.0 * m * g);
       if (!(g > 0.0) || !isfinite(p) || !isfinite(sigma)) {
@@ -327,17 +357,15 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
 
 // End of the last pass of a sweep: the workgroup that finishes last (of every
 // chain) advances the sweep index, after every workgroup has read it.
+// The sweep counter has two slots so that no pass needs a grid-wide barrier:
+// the z-pass reads slot 0 and copies it to slot 1, the forward y-pass (which
+// reads neither) sets slot 0 to slot 1 + 1, and the x-pass and the P draw read
+// slot 1.  Kernel boundaries on the stream order every write before the reads
+// that follow it.
 template <typename R>
-__device__ __forceinline__ void sweep_done(const SweepArgs<R>& a) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t total = gridDim.x * gridDim.y * gridDim.z;
-    if (atomicAdd(a.ctr + 1, 1u) == total - 1) {
-      atomicExch(a.ctr + 1, 0u);
-      atomicAdd(a.ctr, 1u);
-    }
-  }
+__device__ __forceinline__ void advance_sweep(const SweepArgs<R>& a) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+    a.ctr[0] = a.ctr[1] + 1u;
 }
 
 // Table from the current P of every chain (set-up and state restore).
@@ -367,10 +395,11 @@ ypass_kernel(SweepArgs<R> a) {
   if (INV) {
     if (blk < a.nb) {
       pk_draw_block<R, NT>(a, blk, blockIdx.z, reinterpret_cast<double*>(lds));
-      sweep_done(a);
       return;
     }
     blk -= a.nb;
+  } else {
+    advance_sweep(a);
   }
   const int tid = threadIdx.x;
   cx<R>* base = a.spec + static_cast<size_t>(blockIdx.z) * a.spec_stride +
@@ -390,7 +419,6 @@ ypass_kernel(SweepArgs<R> a) {
     TL::template out_pos<false>(tid, e, pen, n);
     base[pen * N + n] = v[e];
   }
-  if (INV) sweep_done(a);
 }
 
 // ---------------------------------------------------------------- x split
@@ -408,16 +436,22 @@ __host__ __device__ constexpr bool split_x() { return N >= 32 && N <= 256; }
 
 // Forward y-pass with x stage A (INV = false), or inverse x stage A with the
 // inverse y-pass (INV = true, plus the P(k) step in the first nb workgroups).
-// Workgroup = one (kz, q): the NA y pencils of rows ix = q + 16 r.
+// Workgroup = G units (kz, q), q = q0 .. q0 + G - 1: each the NA y pencils of
+// rows ix = q + 16 r.
 template <typename R, int N>
 struct YSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
   static constexpr int EPT = ept<N>();
-  static constexpr int NT = NA * N / EPT;
+  static constexpr int TPU = NA * N / EPT;           // threads per (kz, q) unit
   static constexpr int COLS = EPT / NA;    // columns per thread in the x-stage layout
   static constexpr int PADS = pow2<Radices<N>::r[0]>() ? ilog2(Radices<N>::r[0]) : 2;
   static constexpr int PSTR = N + (N >> PADS);
-  using TL = Tile<N, NA, NT, false, PSTR, PADS>;
+  // units per workgroup: up to 256 threads and 48 KB of LDS
+  static constexpr int GCAP_T = 256 / TPU;
+  static constexpr int GCAP_L = 49152 / (NA * PSTR * 2 * static_cast<int>(sizeof(R)));
+  static constexpr int G = pow2_divisor(16, GCAP_T < GCAP_L ? GCAP_T : GCAP_L);
+  static constexpr int NT = G * TPU;
+  using TL = Tile<N, G * NA, NT, false, PSTR, PADS>;
 };
 
 template <typename R, int N, bool INV>
@@ -425,31 +459,36 @@ __global__ void __launch_bounds__((YSTile<R, N>::NT))
 ysplit_kernel(SweepArgs<R> a) {
   using T = YSTile<R, N>;
   using TL = typename T::TL;
-  constexpr int NA = T::NA, NT = T::NT, EPT = T::EPT, COLS = T::COLS;
-  __shared__ cx<R> lds[NA * T::PSTR];
+  constexpr int NA = T::NA, NT = T::NT, EPT = T::EPT, COLS = T::COLS, G = T::G, TPU = T::TPU;
+  __shared__ cx<R> lds[G * NA * T::PSTR];
   __shared__ cx<R> tw[N];
-  static_assert(NA * T::PSTR * sizeof(cx<R>) >= NT * sizeof(double), "reduction space");
+  static_assert(G * NA * T::PSTR * sizeof(cx<R>) >= NT * sizeof(double), "reduction space");
   int blk = blockIdx.x;
   if (INV) {
     if (blk < a.nb) {
       pk_draw_block<R, NT>(a, blk, blockIdx.z, reinterpret_cast<double*>(lds));
-      sweep_done(a);
       return;
     }
     blk -= a.nb;
+  } else {
+    advance_sweep(a);
   }
   const int tid = threadIdx.x;
-  const int kz = blk / 16, q = blk % 16;
+  const int kz = blk / (16 / G), q0 = (blk % (16 / G)) * G;
+  const int ug = tid / TPU, ut = tid % TPU;   // this thread's unit and rank in it (stage A)
+  const int q = q0 + ug;
   cx<R>* plane = a.spec + static_cast<size_t>(blockIdx.z) * a.spec_stride +
                  static_cast<size_t>(kz) * N * N;
   load_twiddles(tw, a.tw, N, NT);
   cx<R> v[EPT];
+  // pencil pen of the y transform = unit pen / NA, row q0 + pen / NA + 16 (pen % NA)
+  auto row_of = [&](int pen) { return q0 + pen / NA + 16 * (pen % NA); };
   if (!INV) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       int pen = 0, n = 0;
       TL::template in_pos<false>(tid, e, pen, n);
-      v[e] = plane[static_cast<size_t>(q + 16 * pen) * N + n];
+      v[e] = plane[static_cast<size_t>(row_of(pen)) * N + n];
     }
     fft_regs<R, N, TL, NT, false, false>(v, lds, tw);
     __syncthreads();
@@ -462,10 +501,10 @@ ysplit_kernel(SweepArgs<R> a) {
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < COLS; ++j) {
-      const int iy = tid + j * NT;
+      const int iy = ut + j * TPU;
       cx<R>* u = v + j * NA;
 #pragma unroll
-      for (int r = 0; r < NA; ++r) u[r] = lds[TL::lidx(r, iy)];
+      for (int r = 0; r < NA; ++r) u[r] = lds[TL::lidx(ug * NA + r, iy)];
       dft<R, NA, false>(u);
 #pragma unroll
       for (int k1 = 0; k1 < NA; ++k1) {
@@ -477,7 +516,7 @@ ysplit_kernel(SweepArgs<R> a) {
     __syncthreads();   // twiddles in LDS
 #pragma unroll
     for (int j = 0; j < COLS; ++j) {
-      const int iy = tid + j * NT;
+      const int iy = ut + j * TPU;
       cx<R>* u = v + j * NA;
 #pragma unroll
       for (int k1 = 0; k1 < NA; ++k1) {
@@ -489,7 +528,7 @@ ysplit_kernel(SweepArgs<R> a) {
 #pragma unroll
     for (int j = 0; j < COLS; ++j) {
 #pragma unroll
-      for (int r = 0; r < NA; ++r) lds[TL::lidx(r, tid + j * NT)] = v[j * NA + r];
+      for (int r = 0; r < NA; ++r) lds[TL::lidx(ug * NA + r, ut + j * TPU)] = v[j * NA + r];
     }
     __syncthreads();
 #pragma unroll
@@ -504,9 +543,8 @@ ysplit_kernel(SweepArgs<R> a) {
     for (int e = 0; e < EPT; ++e) {
       int pen = 0, n = 0;
       TL::template out_pos<false>(tid, e, pen, n);
-      plane[static_cast<size_t>(q + 16 * pen) * N + n] = v[e];
+      plane[static_cast<size_t>(row_of(pen)) * N + n] = v[e];
     }
-    sweep_done(a);
   }
 }
 
@@ -630,7 +668,7 @@ __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c
   d.qscale = static_cast<float>(4.0 * nb * nb / (3.0 * n * n));
   d.nb = nb;
   d.chain = a.chain0 + c;
-  d.sweep = a.ctr[0];
+  d.sweep = a.ctr[1];
   return d;
 }
 
@@ -670,11 +708,7 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
 template <typename R, int N>
 struct XSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
-  // columns per workgroup: the largest power of two <= 256 / NA dividing N
-  static constexpr int P = (256 / NA >= 256 && N % 256 == 0) ? 256
-                           : (256 / NA >= 128 && N % 128 == 0) ? 128
-                           : (256 / NA >= 64 && N % 64 == 0)   ? 64
-                           : (256 / NA >= 32 && N % 32 == 0)   ? 32 : 16;
+  static constexpr int P = divisor_below(N, 256 / NA);   // columns per workgroup
   static constexpr int NT = P * NA;
   static constexpr int HG = 2;
   static constexpr int NHIST = ((NT + 63) / 64) * HG;

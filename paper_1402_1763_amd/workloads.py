@@ -164,3 +164,18 @@ def small_workload(n: int, n_bins: int, mask: str = "random", precision: str = "
     return Workload(f"test-{n}^3", n=n, box=box if box is not None else 15.625 * n,
                     n_bins=n_bins, mask=mask, precision=precision, seed=seed,
                     rng_seed=rng_seed, **kw)
+
+
+# Batched independent chains of several grid sides in one graph: per chain its
+# own seed, random mask fraction in [0.1, 0.4] and noise level sigma^2
+# log-uniform in [0.25, 4]; cell 15.625 h^-1 Mpc, P(k) with n = -1.5, 16 bins.
+BATCHED_SIZES = ((64, 32), (48, 8), (80, 8), (96, 8))   # (grid side, chains)
+
+
+def batched_chain(n: int, chain: int, base_seed: int = 3000, precision: str = "fp32") -> Workload:
+    rng = np.random.default_rng(base_seed + 1000 * n + chain)
+    frac = float(rng.uniform(0.1, 0.4))
+    sigma2 = float(np.exp(rng.uniform(np.log(0.25), np.log(4.0))))
+    return Workload(f"batch-{n}^3-{chain}", n=n, box=15.625 * n, n_bins=16, mask="random",
+                    mask_frac=frac, sigma2=sigma2, precision=precision, sweeps=200,
+                    seed=base_seed + 1000 * n + chain, rng_seed=base_seed)

@@ -116,3 +116,28 @@ def test_state_set_resume_close():
     assert n_b == 8 and err_s < 1e-10 and err_p < 1e-10
     for smp in (ref, a, b):
         smp.close()
+
+
+def test_mixed_size_graph_matches_oracle():
+    """Chains of sides 48, 64, 80, 96 (two each) swept by one graph; one chain
+    of every size checked against the oracle after 5 replays."""
+    groups = []
+    for n in (48, 64, 80, 96):
+        ws = [workloads.batched_chain(n, c) for c in range(2)]
+        pbs = [workloads.make_problem(w) for w in ws]
+        smp = binding.Sampler([pb["data"] for pb in pbs], [pb["noise_var"] for pb in pbs],
+                              [pb["pk_init"] for pb in pbs], 16, ws[0].box, seed=ws[0].rng_seed,
+                              precision="fp32")
+        groups.append((ws, pbs, smp))
+    g = binding.SweepGraph([grp[2] for grp in groups])
+    g.launch(5)
+    for ws, pbs, smp in groups:
+        c = 1
+        s_gpu, p_gpu, done = smp.state(c)
+        s_ref, p_ref = run_oracle(ws[c], pbs[c], 5, chain=c)
+        err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+        print(f"  n={ws[c].n} chain {c}: err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
+        assert done == 5 and err_s < TOL["fp32"] and err_p < TOL["fp32"]
+    g.close()
+    for grp in groups:
+        grp[2].close()
