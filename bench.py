@@ -258,6 +258,10 @@ def main():
                    "sweep_bytes_algorithmic": sweep_bytes,
                    "sweep_hbm_frac": round(sweep_bytes / (ms_per_step * 1e-3) / 1e9
                                            / HBM_PEAK_GBS, 4),
+                   # the same rate priced at a five-pass schedule's 48.25 B/voxel
+                   "sweep_hbm_frac_5pass_bytes": round(48.25 * w.m * real_bytes / 4
+                                                       / (ms_per_step * 1e-3) / 1e9
+                                                       / HBM_PEAK_GBS, 4),
                    "wall_s_timed_region": round(wall_s, 4)},
         "roofline": roofline,
     }
