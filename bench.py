@@ -159,6 +159,112 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def wiener_grad_bytes(n: int, real_bytes: int, n_bins: int, n_iter: int, every: int) -> int:
+    """Algorithmic HBM bytes of one chi2 forward + backward run of the
+    messenger Wiener filter (K iterations, checkpoint every E): K plain
+    iterations, K recomputed ones that store t^, K adjoint iterations that
+    read it back and accumulate the adjoint field, plus set-up and read-out."""
+    m = n ** 3
+    spec = 2 * real_bytes * (n // 2 + 1) * n * n  # half-complex field
+    coef = 2 * real_bytes * m                      # (alpha, beta) per voxel
+    field = real_bytes * m                         # one real field
+    n_wg_x = (n // 2 + 1) * (n // x_columns(n))
+    partials = 2 * n_wg_x * n_bins * 8
+    n_ckpt = -(-n_iter // every)
+    plain = 8 * spec + coef                        # z, y, x, y passes
+    store = plain + spec                           # + t^ written
+    adjoint = plain + spec + 2 * field + partials  # + t^ read, adjoint field summed
+    forward_extra = (coef + 8 * m + coef           # data -> (alpha, beta)
+                     + spec + 2 * spec * n_ckpt    # zero start, checkpoint copies
+                     + spec + field                # s_K read-out
+                     + coef + 8 * m + field)       # chi2
+    backward_extra = (field + spec + 2 * spec * n_ckpt   # zeroing, checkpoint restores
+                      + spec + field                     # s_K read-out
+                      + spec + 2 * field                 # last adjoint field summed
+                      + coef + 8 * m + 2 * field + 8 * m)  # d chi2 / d d
+    return n_iter * (plain + store + adjoint) + forward_extra + backward_extra
+
+
+def bench_wiener(args):
+    """chi2 of the messenger Wiener filter and its gradient with respect to P
+    and d: 128^3 survey problem, 32 bins, 50 iterations, checkpoint every 10."""
+    import torch
+
+    from paper_1402_1763_amd import binding, workloads
+    torch.cuda.set_device(0)
+    w = workloads.SURVEY_128_FP32
+    n_iter, every = 50, 10
+    pb = workloads.make_problem(w)
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision="fp32", sample_pk=False)
+    pk = torch.from_numpy(workloads.power_spectrum(workloads.bin_centres(w), w)).cuda()
+    d = torch.from_numpy(pb["data"]).cuda()
+    wf = binding.WienerFilter(smp, n_iter, every)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        wf.forward(d, pk)
+        wf.backward(d)
+    torch.cuda.synchronize()
+    start, mid, stop = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    fwd_ms = 0.0
+    start.record(stream)
+    for _ in range(args.steps):
+        chi2, _ = wf.forward(d, pk)
+        gd, gp = wf.backward(d)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    start.record(stream)
+    wf.forward(d, pk)
+    mid.record(stream)
+    wf.backward(d)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = start.elapsed_time(mid), mid.elapsed_time(stop)
+    assert np.isfinite(float(chi2)) and bool(torch.isfinite(gp).all())
+    nbytes = wiener_grad_bytes(w.n, 4, w.n_bins, n_iter, every)
+    out = {
+        "metric": "messenger Wiener-filter chi2 + gradient evaluations/s (128^3, 50 iterations, "
+                  "checkpoint every 10)",
+        "value": round(1000.0 / ms, 2), "unit": "evaluations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wiener-grad-128^3-fp32-survey", "n": w.n, "n_bins": w.n_bins,
+                   "iterations": n_iter, "ckpt_every": every,
+                   "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
+                   "iterations_per_s": round(3 * n_iter * 1000.0 / ms, 1),
+                   "bytes_algorithmic": nbytes,
+                   "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = wiener_cpu_baseline(w, pb, n_iter)
+    print(json.dumps(out), flush=True)
+
+
+def wiener_cpu_baseline(w, pb, n_iter: int) -> dict:
+    """The oracle's reverse-mode gradient on the same problem, 5 iterations,
+    scaled to 50."""
+    ncores = len(os.sched_getaffinity(0))
+    os.environ["ORACLE_FFT_WORKERS"] = str(ncores)
+    from oracle import adjoint, sampler
+    prob = sampler.make_problem(pb["data"], pb["noise_var"], w.n_bins, w.box, w.rng_seed)
+    p_grid = workloads_power(w) / w.cell_volume
+    k = 5
+    t0 = time.perf_counter()
+    adjoint.wf_gradient(prob, p_grid, k)
+    dt = (time.perf_counter() - t0) * n_iter / k
+    return {"value": round(1.0 / dt, 5), "unit": "evaluations/s", "cores": ncores,
+            "kind": "oracle",
+            "sample": f"oracle chi2 + reverse-mode gradient, {k} iterations of the same 128^3 "
+                      f"problem, time scaled by {n_iter}/{k} (FP64, scipy.fft with {ncores} workers)"}
+
+
+def workloads_power(w):
+    from paper_1402_1763_amd import workloads
+    return workloads.power_spectrum(workloads.bin_centres(w), w)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +299,8 @@ def main():
 
     if args.workload == "gibbs-batched-mixed":
         return bench_batched(args)
+    if args.workload == "wiener-grad-128^3-fp32-survey":
+        return bench_wiener(args)
     w = workloads.WORKLOADS[args.workload]
     pb = workloads.make_problem(w)
     torch.cuda.set_device(0)

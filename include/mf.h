@@ -182,6 +182,53 @@ mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, 
 mf_status mf_graph_launch(mf_graph* g, int32_t n_sweeps, void* stream);
 void mf_graph_destroy(mf_graph* g);
 
+/* Deterministic messenger Wiener filter and its adjoint (grid sides 32 to
+ * 256).
+ *
+ * With every unit normal of the sweep set to zero and P held fixed, one
+ * sweep becomes the iteration s_{k+1} = C (alpha s_k + beta): the means of
+ * the messenger and signal conditionals (Sec. 3.1).  Here C = F^-1 diag(f) F
+ * with f_b = P_b / (P_b + tau) and f = 0 at k = 0, alpha = 1 - tau / N_i and
+ * beta = tau d_i / N_i on observed voxels, and (1, 0) elsewhere.  The
+ * iteration converges to the Wiener filter S (S + N)^-1 d.  Starting from
+ * s_0 = 0, K iterations give s_K, and the loss is
+ *   chi2_K = sum_i d_i (d_i - s_K,i) / N_i   over observed voxels,
+ * which tends to d^T (S + N)^-1 d as K grows.  The noise model (N_i, the
+ * mask and tau) is chain `chain`'s; d and P are inputs of each call.
+ *
+ * mf_wiener_workspace_bytes: size of the caller-owned device workspace for K
+ *   iterations with a checkpoint every `ckpt_every`.  It holds ceil(K / E)
+ *   checkpoints plus E stored spectra, about (ceil(K/E) + E + 6) * 8 M bytes
+ *   in FP32 mode.
+ * mf_wiener_forward: d (FP64, M, [ix][iy][iz]; ignored where unobserved) and
+ *   pk (FP64, n_bins, physical units) are device arrays.  Writes chi2_K to
+ *   the device double `chi2` and, when `s_out` (device FP64, M) is not NULL,
+ *   s_K.  Checkpoints of s_k every `ckpt_every` iterations stay in the
+ *   workspace for mf_wiener_backward.  The chain's Gibbs state is not
+ *   touched.
+ * mf_wiener_backward: the gradient of the last forward run's chi2_K with
+ *   respect to d (device FP64, M; zero where unobserved) and to P_b (device
+ *   FP64, n_bins, physical units).  It takes the same d and the same
+ *   workspace as that run and recomputes each segment from its checkpoint:
+ *   2 K iterations.
+ *
+ * Both calls enqueue on `stream` without synchronising.  They use the
+ * problem's state staging buffer and chain 0's shell partials as scratch, so
+ * they must not overlap sweeps or state calls on the same problem.
+ * Errors:
+ *  - MF_E_UNSUPPORTED_SIZE for grid sides outside 32..256;
+ *  - MF_E_STATE for a bad chain, or a backward call without a matching
+ *    forward run;
+ *  - MF_E_WORKSPACE for a workspace that is too small or not aligned;
+ *  - MF_E_INVALID_ARG, MF_E_DEVICE. */
+mf_status mf_wiener_workspace_bytes(const mf_problem* p, int32_t n_iter, int32_t ckpt_every,
+                                    size_t* bytes);
+mf_status mf_wiener_forward(mf_problem* p, int32_t chain, const double* d, const double* pk,
+                            int32_t n_iter, int32_t ckpt_every, void* workspace, size_t ws_bytes,
+                            double* chi2, double* s_out, void* stream);
+mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void* workspace,
+                             size_t ws_bytes, double* grad_d, double* grad_pk, void* stream);
+
 /* Release the handle (not the workspace).  NULL is ignored. */
 void mf_destroy_problem(mf_problem* p);
 

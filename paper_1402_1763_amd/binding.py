@@ -79,6 +79,15 @@ SIGNATURES = {
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "mf_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mf_graph_destroy": (None, [ctypes.c_void_p]),
+    "mf_wiener_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_wiener_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "mf_wiener_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "mf_destroy_problem": (None, [ctypes.c_void_p]),
     "mf_last_error": (ctypes.c_char_p, []),
 }
@@ -266,6 +275,31 @@ def mf_graph_destroy(graph: int):
         load().mf_graph_destroy(ctypes.c_void_p(graph))
 
 
+def mf_wiener_workspace_bytes(handle: int, n_iter: int, ckpt_every: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().mf_wiener_workspace_bytes(ctypes.c_void_p(handle), n_iter, ckpt_every,
+                                            ctypes.byref(out)))
+    return out.value
+
+
+def mf_wiener_forward(handle: int, chain: int, d_ptr: int, pk_ptr: int, n_iter: int,
+                      ckpt_every: int, ws_ptr: int, ws_bytes: int, chi2_ptr: int,
+                      s_ptr: Optional[int], stream=None):
+    _check(load().mf_wiener_forward(ctypes.c_void_p(handle), chain, ctypes.c_void_p(d_ptr),
+                                    ctypes.c_void_p(pk_ptr), n_iter, ckpt_every,
+                                    ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(chi2_ptr),
+                                    ctypes.c_void_p(s_ptr or None),
+                                    ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mf_wiener_backward(handle: int, chain: int, d_ptr: int, ws_ptr: int, ws_bytes: int,
+                       grad_d_ptr: int, grad_pk_ptr: int, stream=None):
+    _check(load().mf_wiener_backward(ctypes.c_void_p(handle), chain, ctypes.c_void_p(d_ptr),
+                                     ctypes.c_void_p(ws_ptr), ws_bytes,
+                                     ctypes.c_void_p(grad_d_ptr), ctypes.c_void_p(grad_pk_ptr),
+                                     ctypes.c_void_p(_stream_ptr(stream))))
+
+
 def mf_destroy_problem(handle: int):
     if handle:
         load().mf_destroy_problem(ctypes.c_void_p(handle))
@@ -362,3 +396,50 @@ class SweepGraph:
             self.close()
         except Exception:
             pass
+
+
+class WienerFilter:
+    """The deterministic messenger Wiener filter of one chain of a Sampler
+    (its noise model: N, mask, tau), n_iter iterations from s = 0 with a
+    checkpoint every ckpt_every, and its adjoint.  d and pk are float64 cuda
+    tensors ((N, N, N) and (n_bins,), P in physical units)."""
+
+    def __init__(self, sampler: "Sampler", n_iter: int, ckpt_every: int, chain: int = 0):
+        import torch
+        self.sampler, self.n_iter, self.ckpt_every, self.chain = sampler, n_iter, ckpt_every, chain
+        self.ws_bytes = mf_wiener_workspace_bytes(sampler.handle, n_iter, ckpt_every)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
+                                     device=sampler.workspace.device)
+        self._ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.generation = 0      # increments with every forward run
+
+    def _check_inputs(self, d, pk):
+        import torch
+        n, nb = self.sampler.n, self.sampler.n_bins
+        for name, t, shape in (("d", d, (n, n, n)), ("pk", pk, (nb,))):
+            if (t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape
+                    or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 cuda tensor of shape {shape}")
+
+    def forward(self, d, pk, want_s: bool = False):
+        """chi2_K as a 0-dim tensor, and s_K when want_s."""
+        import torch
+        self._check_inputs(d, pk)
+        chi2 = torch.empty((), dtype=torch.float64, device=d.device)
+        s = torch.empty_like(d) if want_s else None
+        mf_wiener_forward(self.sampler.handle, self.chain, d.data_ptr(), pk.data_ptr(),
+                          self.n_iter, self.ckpt_every, self._ptr, self.ws_bytes,
+                          chi2.data_ptr(), s.data_ptr() if want_s else None,
+                          self.sampler.stream.cuda_stream)
+        self.generation += 1
+        return chi2, s
+
+    def backward(self, d):
+        """(d chi2/d d, d chi2/d pk) of the last forward run (same d)."""
+        import torch
+        grad_d = torch.empty_like(d)
+        grad_pk = torch.empty(self.sampler.n_bins, dtype=torch.float64, device=d.device)
+        mf_wiener_backward(self.sampler.handle, self.chain, d.data_ptr(), self._ptr,
+                           self.ws_bytes, grad_d.data_ptr(), grad_pk.data_ptr(),
+                           self.sampler.stream.cuda_stream)
+        return grad_d, grad_pk

@@ -11,10 +11,12 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mf.h"
 #include "sweep_kernels.hpp"
+#include "wiener_kernels.hpp"
 
 namespace {
 
@@ -175,6 +177,12 @@ std::vector<double> twiddles(int n) {
 
 }  // namespace
 
+// The last Wiener forward run, whose checkpoints a backward run reads.
+struct WienerRun {
+  const void* gws = nullptr;
+  int chain = -1, n_iter = 0, every = 0;
+};
+
 struct mf_problem {
   mf_chain_desc desc;
   Layout L;
@@ -182,6 +190,7 @@ struct mf_problem {
   char* ws;
   std::vector<double> tau;
   uint64_t sweep;
+  WienerRun wiener;
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
 
@@ -212,10 +221,17 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   a.chain0 = p->desc.chain_id;
   a.key0 = static_cast<uint32_t>(p->desc.seed);
   a.key1 = static_cast<uint32_t>(p->desc.seed >> 32);
+  a.cs = R(1);
+  a.cb = R(1);
+  a.advance = 1;
+  a.pk_mode = mf::kPkDraw;
   return a;
 }
 
-enum KernelId { kZ = 0, kYF = 1, kX = 2, kYI = 3, kZSet = 10, kZGet = 11, kTable = 12 };
+enum KernelId {
+  kZ = 0, kYF = 1, kX = 2, kYI = 3, kZSet = 10, kZGet = 11, kTable = 12,
+  kZDetK = 13, kZAccK = 14, kXDetK = 15, kXAdjK = 16
+};
 
 template <typename R, int N>
 void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
@@ -237,6 +253,12 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
     case kZGet:
       hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZGetState>), zgrid1, dim3(ZT::NT), 0, st, a);
       break;
+    case kZDetK:
+      hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZDet>), zgrid, dim3(ZT::NT), 0, st, a);
+      break;
+    case kZAccK:
+      hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZAccum>), zgrid, dim3(ZT::NT), 0, st, a);
+      break;
     case kYF:
       if constexpr (split)
         hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 / YS::G * (N / 2 + 1), 1, nch),
@@ -254,10 +276,20 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
         hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>),
                            dim3((N / 2 + 1) * N / YT::NPEN + a.nb, 1, nch), dim3(YT::NT), 0, st, a);
       break;
+    case kXDetK:
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet>), dim3(N / XS::P, N / 2 + 1, nch),
+                           dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+      break;
+    case kXAdjK:
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXAdj>), dim3(N / XS::P, N / 2 + 1, nch),
+                           dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+      break;
     case kX:
       if constexpr (split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N>), dim3(N / XS::P, N / 2 + 1, nch), dim3(XS::NT),
-                           XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample>), dim3(N / XS::P, N / 2 + 1, nch),
+                           dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       else
         hipLaunchKernelGGL((mf::xpass_kernel<R, N>), dim3(N / XT::P, N / 2 + 1, nch), dim3(XT::NT),
                            XT::NHIST * a.nb * sizeof(double) + tables, st, a);
@@ -797,5 +829,260 @@ mf_status mf_graph_launch(mf_graph* g, int32_t n_sweeps, void* stream) {
 void mf_graph_destroy(mf_graph* g) { delete g; }
 
 const char* mf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- Wiener filter
+namespace {
+
+// Wiener workspace: scratch and per-run buffers, each 256-byte aligned.
+struct WLayout {
+  size_t partial, pkg, gacc, table, wcoef, fwd, adj, ckpt, aux, acc, total;
+  size_t spec_bytes;
+  int nblk, n_ckpt;
+};
+
+WLayout wiener_layout(const mf_problem* p, int n_iter, int every) {
+  const size_t rs = p->fp64() ? 8 : 4;
+  const size_t n = p->desc.n, m = n * n * n, nb = p->desc.n_bins;
+  WLayout W{};
+  W.nblk = static_cast<int>((m / 2 + mf::kWienerThreads - 1) / mf::kWienerThreads);
+  W.n_ckpt = (n_iter + every - 1) / every;
+  W.spec_bytes = p->L.spec_stride * 2 * rs;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  W.partial = take(static_cast<size_t>(W.nblk) * 8);
+  W.pkg = take(nb * 8);
+  W.gacc = take(nb * 8);
+  W.table = take(nb * 2 * rs);
+  W.wcoef = take(2 * m * rs);
+  W.fwd = take(W.spec_bytes);
+  W.adj = take(W.spec_bytes);
+  W.ckpt = take(static_cast<size_t>(W.n_ckpt) * W.spec_bytes);
+  W.aux = take(static_cast<size_t>(every) * W.spec_bytes);
+  W.acc = take(m * rs);
+  W.total = off;
+  return W;
+}
+
+mf_status check_wiener(const mf_problem* p, int chain, int n_iter, int every, const void* gws,
+                       size_t gws_bytes, WLayout* W) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (p->desc.n < 32 || p->desc.n > 256)
+    return fail(MF_E_UNSUPPORTED_SIZE, "the Wiener iteration supports grid sides 32 to 256 (got %d)",
+                p->desc.n);
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  if (n_iter < 1 || every < 1 || every > n_iter)
+    return fail(MF_E_INVALID_ARG, "need n_iter >= 1 and 1 <= ckpt_every <= n_iter");
+  *W = wiener_layout(p, n_iter, every);
+  if (!gws || reinterpret_cast<uintptr_t>(gws) % kAlign != 0)
+    return fail(MF_E_WORKSPACE, "Wiener workspace NULL or not 256-byte aligned");
+  if (gws_bytes < W->total)
+    return fail(MF_E_WORKSPACE, "Wiener workspace too small: %zu < %zu", gws_bytes, W->total);
+  return MF_OK;
+}
+
+template <typename F>
+void with_n(int n, F&& f) {
+  switch (n) {
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 48: f(std::integral_constant<int, 48>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 80: f(std::integral_constant<int, 80>{}); break;
+    case 96: f(std::integral_constant<int, 96>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    default: break;
+  }
+}
+
+// Sweep arguments of one deterministic iteration of chain `chain` on the
+// spectrum `spec` (one chain, grid z = 1).
+template <typename R>
+mf::SweepArgs<R> wiener_args(const mf_problem* p, int chain, char* g, const WLayout& W) {
+  mf::SweepArgs<R> a = args_of<R>(p);
+  a.coef = reinterpret_cast<const R*>(g + W.wcoef);
+  a.table = reinterpret_cast<R*>(g + W.table);
+  a.pk = reinterpret_cast<double*>(g + W.pkg);
+  a.gacc = reinterpret_cast<double*>(g + W.gacc);
+  a.tau = reinterpret_cast<const double*>(p->ws + p->L.tau) + chain;
+  a.status = reinterpret_cast<uint32_t*>(p->ws + p->L.status) + chain;
+  a.chain0 = p->desc.chain_id + chain;
+  a.advance = 0;
+  a.staging_chain = 0;
+  return a;
+}
+
+mf_status check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MF_E_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+  return MF_OK;
+}
+
+// One iteration s' = C (cs alpha s + cb beta) on `spec`.  Forward (adj =
+// false): t^ goes to aux when aux is set.  Adjoint (adj = true): the per-bin
+// sums of Re(conj(t^) aux) are added to gacc, and s is added to acc when set.
+template <typename R>
+mf_status wiener_iter(mf_problem* p, mf::SweepArgs<R> a, mf::cx<R>* spec, mf::cx<R>* aux, bool adj,
+                      R cs, R cb, R* acc, hipStream_t st) {
+  a.spec = spec;
+  a.aux = aux;
+  a.acc = acc;
+  a.cs = cs;
+  a.cb = cb;
+  a.pk_mode = adj ? mf::kPkGrad : mf::kPkNone;
+  const int ids[4] = {kZDetK, kYF, adj ? kXAdjK : kXDetK, kYI};
+  for (int id : ids) {
+    launch<R>(id, a, p->desc.n, 1, st);
+    const mf_status r = check_launch("Wiener iteration");
+    if (r != MF_OK) return r;
+  }
+  return MF_OK;
+}
+
+template <typename R>
+mf_status wiener_forward(mf_problem* p, int chain, const double* d, const double* pk, int n_iter,
+                         int every, char* g, const WLayout& W, double* chi2, double* s_out,
+                         hipStream_t st) {
+  const int n = p->desc.n, nb = p->desc.n_bins;
+  const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
+  const double vcell = std::pow(p->desc.box / n, 3), tau = p->tau[chain];
+  auto a = wiener_args<R>(p, chain, g, W);
+  const R* coef = reinterpret_cast<const R*>(p->ws + p->L.coef) + static_cast<size_t>(chain) * 2 * m;
+  with_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL((mf::wiener_coef_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
+                       st, coef, reinterpret_cast<R*>(g + W.wcoef), d, entries);
+  });
+  hipLaunchKernelGGL((mf::wiener_table_kernel<R>), dim3((nb + 63) / 64), dim3(64), 0, st, pk,
+                     reinterpret_cast<double*>(g + W.pkg), reinterpret_cast<R*>(g + W.table), tau,
+                     vcell, static_cast<double>(m), nb);
+  hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st,
+                     reinterpret_cast<R*>(g + W.fwd), W.spec_bytes / sizeof(R));
+  mf_status r = check_launch("Wiener set-up");
+  if (r != MF_OK) return r;
+  auto* fwd = reinterpret_cast<mf::cx<R>*>(g + W.fwd);
+  for (int k = 0; k < n_iter; ++k) {
+    if (k % every == 0)
+      MF_HIP(hipMemcpyAsync(g + W.ckpt + static_cast<size_t>(k / every) * W.spec_bytes, fwd,
+                            W.spec_bytes, hipMemcpyDeviceToDevice, st));
+    if ((r = wiener_iter<R>(p, a, fwd, nullptr, false, R(1), R(1), nullptr, st)) != MF_OK) return r;
+  }
+  a.spec = fwd;
+  launch<R>(kZGet, a, n, 1, st);
+  const R* s = reinterpret_cast<const R*>(p->ws + p->L.staging);
+  with_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL((mf::wiener_chi2_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0, st,
+                       reinterpret_cast<const R*>(g + W.wcoef), d, s, tau,
+                       reinterpret_cast<double*>(g + W.partial), s_out, entries);
+  });
+  hipLaunchKernelGGL(mf::sum_partials_kernel, dim3(1), dim3(mf::kWienerThreads), 0, st,
+                     reinterpret_cast<const double*>(g + W.partial), W.nblk, chi2);
+  return check_launch("Wiener chi2");
+}
+
+template <typename R>
+mf_status wiener_backward(mf_problem* p, int chain, const double* d, char* g, const WLayout& W,
+                          double* grad_d, double* grad_pk, hipStream_t st) {
+  const int n = p->desc.n, nb = p->desc.n_bins;
+  const int n_iter = p->wiener.n_iter, every = p->wiener.every;
+  const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
+  const double vcell = std::pow(p->desc.box / n, 3), tau = p->tau[chain];
+  auto a = wiener_args<R>(p, chain, g, W);
+  auto* fwd = reinterpret_cast<mf::cx<R>*>(g + W.fwd);
+  auto* adj = reinterpret_cast<mf::cx<R>*>(g + W.adj);
+  R* acc = reinterpret_cast<R*>(g + W.acc);
+  auto slot = [&](int j) { return reinterpret_cast<mf::cx<R>*>(g + W.aux + static_cast<size_t>(j) * W.spec_bytes); };
+  hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<double*>(g + W.gacc), static_cast<size_t>(nb));
+  hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st, acc, m);
+  hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st,
+                     reinterpret_cast<R*>(adj), W.spec_bytes / sizeof(R));
+  mf_status r = check_launch("Wiener adjoint set-up");
+  if (r != MF_OK) return r;
+  const R neg_inv_tau = static_cast<R>(-1.0 / tau);
+  for (int sg = W.n_ckpt - 1; sg >= 0; --sg) {
+    const int k0 = sg * every, k1 = std::min(n_iter, k0 + every);
+    MF_HIP(hipMemcpyAsync(fwd, g + W.ckpt + static_cast<size_t>(sg) * W.spec_bytes, W.spec_bytes,
+                          hipMemcpyDeviceToDevice, st));
+    for (int k = k0; k < k1; ++k)
+      if ((r = wiener_iter<R>(p, a, fwd, slot(k - k0), false, R(1), R(1), nullptr, st)) != MF_OK)
+        return r;
+    if (sg == W.n_ckpt - 1) {   // fwd now holds s_K
+      a.spec = fwd;
+      launch<R>(kZGet, a, n, 1, st);
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      // step k maps g_{k+1} to r_k = C g_{k+1}: g_K = -w d = -beta / tau, and
+      // g_{k+1} = alpha r_{k+1} otherwise (r_{k+1} then joins the sum)
+      r = (k == n_iter - 1)
+              ? wiener_iter<R>(p, a, adj, slot(k - k0), true, R(0), neg_inv_tau, nullptr, st)
+              : wiener_iter<R>(p, a, adj, slot(k - k0), true, R(1), R(0), acc, st);
+      if (r != MF_OK) return r;
+    }
+  }
+  a.spec = adj;
+  a.acc = acc;
+  launch<R>(kZAccK, a, n, 1, st);   // adds r_0
+  const R* s = reinterpret_cast<const R*>(p->ws + p->L.staging);
+  with_n(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL((mf::wiener_grad_d_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
+                       st, reinterpret_cast<const R*>(g + W.wcoef), d, s, acc, tau, grad_d, entries);
+  });
+  hipLaunchKernelGGL(mf::wiener_grad_pk_kernel, dim3((nb + 63) / 64), dim3(64), 0, st,
+                     reinterpret_cast<const double*>(g + W.gacc),
+                     reinterpret_cast<const double*>(g + W.pkg), tau, vcell, nb, grad_pk);
+  return check_launch("Wiener gradient");
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_wiener_workspace_bytes(const mf_problem* p, int32_t n_iter, int32_t ckpt_every,
+                                    size_t* bytes) {
+  if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (n_iter < 1 || ckpt_every < 1 || ckpt_every > n_iter)
+    return fail(MF_E_INVALID_ARG, "need n_iter >= 1 and 1 <= ckpt_every <= n_iter");
+  *bytes = wiener_layout(p, n_iter, ckpt_every).total;
+  return MF_OK;
+}
+
+mf_status mf_wiener_forward(mf_problem* p, int32_t chain, const double* d, const double* pk,
+                            int32_t n_iter, int32_t ckpt_every, void* workspace, size_t ws_bytes,
+                            double* chi2, double* s_out, void* stream) {
+  WLayout W{};
+  mf_status r = check_wiener(p, chain, n_iter, ckpt_every, workspace, ws_bytes, &W);
+  if (r != MF_OK) return r;
+  if (!d || !pk || !chi2) return fail(MF_E_INVALID_ARG, "d, pk and chi2 must be device pointers");
+  p->wiener = WienerRun{};
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* g = static_cast<char*>(workspace);
+  r = p->fp64() ? wiener_forward<double>(p, chain, d, pk, n_iter, ckpt_every, g, W, chi2, s_out, hs)
+                : wiener_forward<float>(p, chain, d, pk, n_iter, ckpt_every, g, W, chi2, s_out, hs);
+  if (r == MF_OK) p->wiener = WienerRun{workspace, chain, n_iter, ckpt_every};
+  return r;
+}
+
+mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void* workspace,
+                             size_t ws_bytes, double* grad_d, double* grad_pk, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (p->wiener.gws == nullptr || p->wiener.gws != workspace || p->wiener.chain != chain)
+    return fail(MF_E_STATE, "no Wiener forward run of chain %d with this workspace", chain);
+  WLayout W{};
+  mf_status r = check_wiener(p, chain, p->wiener.n_iter, p->wiener.every, workspace, ws_bytes, &W);
+  if (r != MF_OK) return r;
+  if (!d || !grad_d || !grad_pk) return fail(MF_E_INVALID_ARG, "d, grad_d and grad_pk must be device pointers");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* g = static_cast<char*>(workspace);
+  return p->fp64() ? wiener_backward<double>(p, chain, d, g, W, grad_d, grad_pk, hs)
+                   : wiener_backward<float>(p, chain, d, g, W, grad_d, grad_pk, hs);
+}
 
 }  // extern "C"

@@ -52,9 +52,18 @@ struct SweepArgs {
   uint32_t* ctr;          // [0] next sweep's index, [1] index of the sweep in flight
   uint32_t chain0;
   uint32_t key0, key1;
+  // Deterministic messenger iteration (the Wiener filter) and its adjoint:
+  R cs, cb;               // z-pass forms t = cs alpha s + cb beta (no draw)
+  R* acc;                 // z-pass order [entry][2]: adds s before the messenger step
+  cx<R>* aux;             // x-pass layout: t^ of one iteration (stored or read)
+  double* gacc;           // [chain][nb] accumulated d chi2 / d f_b
+  int32_t advance;        // the forward y-pass advances the sweep counter
+  int32_t pk_mode;        // P(k) workgroups of the inverse y-pass (PkMode)
 };
 
-enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2 };
+enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2, kZDet = 3, kZAccum = 4 };
+enum XMode : int { kXSample = 0, kXDet = 1, kXAdj = 2 };
+enum PkMode : int { kPkDraw = 0, kPkNone = 1, kPkGrad = 2 };
 
 // ---------------------------------------------------------------- tiles
 // Largest power of two d <= cap that divides n (at least 1).
@@ -181,6 +190,8 @@ __host__ __device__ inline void zpass_coef_voxel(int tile, int e, int tid, int& 
 // The unit normals of voxel (ix, iy, n) come from Philox counter
 // ((ix N + iy) N/4 + n mod N/4, sweep, 0, chain), normal n div (N/4) of the
 // call; a thread's elements n = q + (N/R_L) r cover all four normals of a call.
+// kZDet replaces the draw by t = cs alpha s + cb beta (the messenger mean for
+// cs = cb = 1) and, if acc is set, first adds s to acc; kZAccum only adds s.
 template <typename R, int N, int MODE>
 __global__ void __launch_bounds__((ZTile<R, N>::NT))
 zpass_kernel(SweepArgs<R> a) {
@@ -195,7 +206,8 @@ zpass_kernel(SweepArgs<R> a) {
   const int blk = blockIdx.x;
   const int iy0 = blk * T::P;
   const int ix0 = blockIdx.y * T::IXB;
-  const int c = (MODE == kZSweep) ? static_cast<int>(blockIdx.z) : a.staging_chain;
+  const int c = (MODE == kZSweep || MODE == kZDet || MODE == kZAccum)
+                    ? static_cast<int>(blockIdx.z) : a.staging_chain;
   cx<R>* spec = a.spec + static_cast<size_t>(c) * a.spec_stride;
   load_twiddles(tw, a.tw, N, NT);
   cx<R> v[EPT];
@@ -220,6 +232,17 @@ zpass_kernel(SweepArgs<R> a) {
       else v[e] = cx<R>{A.x + B.y, B.x - A.y};
     }
     fft_regs<R, N, TL, NT, true, false>(v, lds, tw);
+    if (MODE == kZAccum || (MODE == kZDet && a.acc != nullptr)) {
+      R* acc = a.acc + static_cast<size_t>(c) * a.m +
+               static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 2;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        R* q = acc + (static_cast<size_t>(e) * NT + tid) * 2;
+        q[0] += v[e].x;
+        q[1] += v[e].y;
+      }
+      if (MODE == kZAccum) return;
+    }
     if (MODE == kZGetState) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
@@ -244,6 +267,16 @@ zpass_kernel(SweepArgs<R> a) {
       const size_t ra =
           (static_cast<size_t>(ix0 + pen / NPAIR) * N + iy0 + 2 * (pen % NPAIR)) * N + n;
       v[e] = cx<R>{a.staging[ra] * inv_n, a.staging[ra + N] * inv_n};
+    }
+  } else if (MODE == kZDet) {
+    const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m +
+                    static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 4;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      R cf[4];
+      ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
+      const cx<R> s = v[e];
+      v[e] = cx<R>{a.cs * cf[0] * s.x + a.cb * cf[2], a.cs * cf[1] * s.y + a.cb * cf[3]};
     }
   } else {
     const R tau = static_cast<R>(a.tau[c]);
@@ -317,8 +350,11 @@ __device__ __forceinline__ void write_table(R* tab, int b, double p, double tau,
 // tree in `red`, NTH doubles), forms sigma_b = M^2 sum w |s^/M|^2 and draws
 // P_b = sigma_b / (2 M g), g ~ Gamma(n_b / 2, 1) -- the inverse-gamma
 // conditional of P_b under Jeffreys' prior -- then refreshes (A_b, B_b).
+// With pk_mode == kPkGrad the workgroup instead adds sum_wg partials / M to
+// gacc[b] (the Wiener adjoint's d chi2 / d f_b); kPkNone does nothing.
 template <typename R, int NTH>
 __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int c, double* red) {
+  if (a.pk_mode == kPkNone) return;
   const int tid = threadIdx.x;
   const double* part = a.partials + (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x;
   double s = 0.0;
@@ -335,7 +371,9 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
     if (tid < h) red[tid] += red[tid + h];
     __syncthreads();
   }
-  if (tid == 0) {
+  if (tid == 0 && a.pk_mode == kPkGrad) {
+    a.gacc[static_cast<size_t>(c) * a.nb + b] += red[0] / static_cast<double>(a.m);
+  } else if (tid == 0) {
     const double m = static_cast<double>(a.m);
     const double sigma = red[0] * m * m;
     const double tau = a.tau[c];
@@ -355,8 +393,6 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
   }
 }
 
-// End of the last pass of a sweep: the workgroup that finishes last (of every
-// chain) advances the sweep index, after every workgroup has read it.
 // The sweep counter has two slots so that no pass needs a grid-wide barrier:
 // the z-pass reads slot 0 and copies it to slot 1, the forward y-pass (which
 // reads neither) sets slot 0 to slot 1 + 1, and the x-pass and the P draw read
@@ -364,7 +400,7 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
 // that follow it.
 template <typename R>
 __device__ __forceinline__ void advance_sweep(const SweepArgs<R>& a) {
-  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+  if (a.advance && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
     a.ctr[0] = a.ctr[1] + 1u;
 }
 
@@ -649,6 +685,39 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
   }
 }
 
+// Deterministic counterpart of draw_slot for the Wiener iteration: every mode
+// becomes A_b t^ (the signal conditional's mean, f_b t^ / M).  XM = kXDet
+// stores t^ to aux (when set); XM = kXAdj adds w Re(conj(t^) u^) / 1 to the
+// bin's histogram, u^ read from aux -- the per-bin sum of the adjoint's
+// d chi2 / d f_b (before its 1/M).  aux element e sits at aux[e * astride].
+template <typename R, int N, int RL, int S, int XM>
+__device__ __forceinline__ void filter_slot(cx<R>* v, int q, int iy, int kz, const DrawCtx<R>& d,
+                                            cx<R>* aux, size_t astride) {
+  constexpr int H = N / 2;
+  const double wgt = (kz == 0 || kz == H) ? 1.0 : 2.0;
+  const int my = wavenumber(iy, N);
+  const int r2 = my * my + kz * kz;
+#pragma unroll
+  for (int e = 0; e < RL; ++e) {
+    const int mx = wavenumber(q + S * e, N);
+    const int qq = mx * mx + r2;
+    const cx<R> t = v[e];
+    cx<R> out{R(0), R(0)};
+    if (qq > 0) {
+      const int b = bin_of(qq, d.qthr, d.nb, d.qscale);
+      const R f = d.tab[b].x;
+      out = cx<R>{f * t.x, f * t.y};
+      if (XM == kXAdj) {
+        const cx<R> u = aux[e * astride];
+        atomicAdd(d.hist + b, wgt * (static_cast<double>(t.x) * u.x +
+                                     static_cast<double>(t.y) * u.y));
+      }
+    }
+    if (XM == kXDet && aux != nullptr) aux[e * astride] = t;
+    v[e] = out;
+  }
+}
+
 // Shared prologue / epilogue of the x-pass kernels: LDS tables and per-wave
 // histograms (HG copies per wave by lane), then one partial per workgroup.
 template <typename R, int NT, int NHIST, int HG>
@@ -714,7 +783,7 @@ struct XSTile {
   static constexpr int NHIST = ((NT + 63) / 64) * HG;
 };
 
-template <typename R, int N>
+template <typename R, int N, int XM>
 __global__ void __launch_bounds__((XSTile<R, N>::NT))
 xsplit_kernel(SweepArgs<R> a) {
   using T = XSTile<R, N>;
@@ -733,11 +802,16 @@ xsplit_kernel(SweepArgs<R> a) {
   for (int j = 0; j < 16; ++j) v[j] = base[static_cast<size_t>(j) * N];
   dft<R, 16, false>(v);                 // v[k2] = X[k1 + NA k2]
   __syncthreads();                      // tables and histograms ready
-  draw_slot<R, N, 16, NA>(v, k1, iy0 + col, kz, a, d);
+  if (XM == kXSample) {
+    draw_slot<R, N, 16, NA>(v, k1, iy0 + col, kz, a, d);
+  } else {
+    cx<R>* aux = a.aux == nullptr ? nullptr : a.aux + (base - a.spec);
+    filter_slot<R, N, 16, NA, XM>(v, k1, iy0 + col, kz, d, aux, N);
+  }
   dft<R, 16, true>(v);
 #pragma unroll
   for (int j = 0; j < 16; ++j) base[static_cast<size_t>(j) * N] = v[j];
-  draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x);
+  if (XM != kXDet) draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Whole-transform x-pass (N = 8, 16, 512): workgroup = one kz plane and P

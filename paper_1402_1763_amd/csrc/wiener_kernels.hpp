@@ -1,0 +1,149 @@
+// Kernels around the deterministic messenger iteration (the Wiener filter of
+// the messenger scheme: the Gibbs sweep with every unit normal set to zero and
+// P held fixed) and its adjoint.
+//
+// One iteration maps s_k to s_{k+1} = C (alpha s_k + beta), with
+// C = F^-1 diag(f) F, f_b = P_b / (P_b + tau) per |k| bin, f = 0 at k = 0,
+// alpha = 1 - tau/N_i and beta = tau d_i / N_i on observed voxels, (1, 0)
+// elsewhere (Sec. 3.1: the means of the messenger and signal conditionals).
+// The loss is chi2_K = sum_i w_i d_i (d_i - s_K,i), w_i = 1/N_i (0 where
+// unobserved), which tends to d^T (S + N)^-1 d as K grows.
+//
+// The sweep kernels run the iteration in deterministic modes (kZDet, kXDet,
+// kXAdj, kPkGrad).  The kernels here build the iteration's inputs and finish
+// its outputs; all of them walk the z-pass coefficient order, entry
+// ((tile EPT + e) NT + tid) covering voxels (ix, iya, n) and (ix, iya + 1, n).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sweep_kernels.hpp"
+
+namespace mf {
+
+constexpr int kWienerThreads = 256;
+
+template <typename R, int N>
+__device__ __forceinline__ void entry_voxels(size_t idx, size_t& va, size_t& vb) {
+  using T = ZTile<R, N>;
+  const int tile = static_cast<int>(idx / (static_cast<size_t>(T::EPT) * T::NT));
+  const int rem = static_cast<int>(idx % (static_cast<size_t>(T::EPT) * T::NT));
+  int ix = 0, iya = 0, n = 0;
+  zpass_coef_voxel<R, N>(tile, rem / T::NT, rem % T::NT, ix, iya, n);
+  va = (static_cast<size_t>(ix) * N + iya) * N + n;
+  vb = va + N;
+}
+
+// wcoef = (alpha_a, alpha_b, (1 - alpha_a) d_a, (1 - alpha_b) d_b): the
+// messenger coefficients of the problem's noise model with new data d (FP64,
+// [ix][iy][iz]); beta = tau d / N = (1 - alpha) d.
+template <typename R, int N>
+__global__ void __launch_bounds__(kWienerThreads)
+wiener_coef_kernel(const R* coef, R* wcoef, const double* d, size_t entries) {
+  const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
+  if (idx >= entries) return;
+  size_t va = 0, vb = 0;
+  entry_voxels<R, N>(idx, va, vb);
+  const R aa = coef[idx * 4], ab = coef[idx * 4 + 1];
+  wcoef[idx * 4] = aa;
+  wcoef[idx * 4 + 1] = ab;
+  wcoef[idx * 4 + 2] = static_cast<R>((1.0 - static_cast<double>(aa)) * d[va]);
+  wcoef[idx * 4 + 3] = static_cast<R>((1.0 - static_cast<double>(ab)) * d[vb]);
+}
+
+// Grid-unit P (P / V_cell) and the filter table (A_b = f_b / M, B_b unused).
+template <typename R>
+__global__ void wiener_table_kernel(const double* pk, double* pkg, R* table, double tau,
+                                    double vcell, double m, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double p = pk[b] / vcell;
+  pkg[b] = p;
+  const double f = p / (p + tau);
+  table[2 * b] = static_cast<R>(f / m);
+  table[2 * b + 1] = R(0);
+}
+
+template <typename T>
+__global__ void fill_zero_kernel(T* p, size_t n) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = T(0);
+}
+
+// Fixed-order block sum of kWienerThreads doubles in LDS; returns it on lane 0.
+__device__ __forceinline__ double block_sum(double* red, double x) {
+  const int tid = threadIdx.x;
+  red[tid] = x;
+  __syncthreads();
+  for (int h = kWienerThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Per-block partial sums of chi2 = sum_i w_i d_i (d_i - s_i), w = (1 - alpha)
+// / tau; optionally s_out = s (FP64, [ix][iy][iz]).  s is the iterate in
+// [ix][iy][iz] order (the z-pass state read-out).
+template <typename R, int N>
+__global__ void __launch_bounds__(kWienerThreads)
+wiener_chi2_kernel(const R* wcoef, const double* d, const R* s, double tau, double* partial,
+                   double* s_out, size_t entries) {
+  __shared__ double red[kWienerThreads];
+  const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
+  double x = 0.0;
+  if (idx < entries) {
+    size_t va = 0, vb = 0;
+    entry_voxels<R, N>(idx, va, vb);
+    const double wa = (1.0 - static_cast<double>(wcoef[idx * 4])) / tau;
+    const double wb = (1.0 - static_cast<double>(wcoef[idx * 4 + 1])) / tau;
+    const double sa = s[va], sb = s[vb];
+    if (wa > 0.0) x += wa * d[va] * (d[va] - sa);
+    if (wb > 0.0) x += wb * d[vb] * (d[vb] - sb);
+    if (s_out) {
+      s_out[va] = sa;
+      s_out[vb] = sb;
+    }
+  }
+  const double t = block_sum(red, x);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// out[0] = sum of n partials in a fixed order (one workgroup).
+__global__ void __launch_bounds__(kWienerThreads)
+sum_partials_kernel(const double* partial, int n, double* out) {
+  __shared__ double red[kWienerThreads];
+  double x = 0.0;
+  for (int i = threadIdx.x; i < n; i += kWienerThreads) x += partial[i];
+  const double t = block_sum(red, x);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// d chi2 / d d_i = w_i (2 d_i - s_K,i) + (1 - alpha_i) sum_k r_k,i, where r_k
+// is the adjoint field (acc, z-pass order); zero on unobserved voxels.
+template <typename R, int N>
+__global__ void __launch_bounds__(kWienerThreads)
+wiener_grad_d_kernel(const R* wcoef, const double* d, const R* s, const R* acc, double tau,
+                     double* grad_d, size_t entries) {
+  const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
+  if (idx >= entries) return;
+  size_t va = 0, vb = 0;
+  entry_voxels<R, N>(idx, va, vb);
+  const double oa = 1.0 - static_cast<double>(wcoef[idx * 4]);
+  const double ob = 1.0 - static_cast<double>(wcoef[idx * 4 + 1]);
+  grad_d[va] = oa / tau * (2.0 * d[va] - s[va]) + oa * static_cast<double>(acc[idx * 2]);
+  grad_d[vb] = ob / tau * (2.0 * d[vb] - s[vb]) + ob * static_cast<double>(acc[idx * 2 + 1]);
+}
+
+// d chi2 / d P_b (physical units) = d chi2 / d f_b * tau / (P_b + tau)^2 / V_cell.
+__global__ void wiener_grad_pk_kernel(const double* gacc, const double* pkg, double tau,
+                                      double vcell, int nb, double* grad_pk) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double den = pkg[b] + tau;
+  grad_pk[b] = gacc[b] * tau / (den * den) / vcell;
+}
+
+}  // namespace mf

@@ -1,0 +1,180 @@
+"""GPU tests of the messenger Wiener filter and its adjoint against the oracle
+(oracle/adjoint.py), central finite differences of the GPU forward, and the
+torch autograd wrapper."""
+import numpy as np
+import pytest
+
+from oracle import adjoint
+from paper_1402_1763_amd import binding, workloads
+from tests.gpu_util import TOL, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.load()
+    torch.cuda.set_device(0)
+
+
+def _setup(n, n_bins, precision, mask="random", seed=21, **kw):
+    import torch
+    w = workloads.small_workload(n, n_bins, mask=mask, precision=precision, seed=seed,
+                                 rng_seed=31, **kw)
+    pb = workloads.make_problem(w)
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], n_bins, w.box,
+                          seed=w.rng_seed, precision=precision, sample_pk=False)
+    pk = 0.5 * workloads.power_spectrum(workloads.bin_centres(w), w)
+    d = torch.from_numpy(pb["data"]).cuda()
+    pk_t = torch.from_numpy(pk).cuda()
+    return w, pb, smp, d, pk, pk_t
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision,n,mask", [("fp64", 32, "random"), ("fp32", 32, "random"),
+                                              ("fp64", 48, "random"), ("fp32", 80, "none"),
+                                              ("fp32", 64, "survey")])
+def test_gradient_matches_oracle(precision, n, mask):
+    import torch
+    k, every = 12, 5
+    w, pb, smp, d, pk, pk_t = _setup(n, 8, precision, mask=mask)
+    print(f"wiener n={n} {precision} {mask} K={k} E={every}", flush=True)
+    wf = binding.WienerFilter(smp, k, every)
+    chi2, s_k = wf.forward(d, pk_t, want_s=True)
+    grad_d, grad_pk = wf.backward(d)
+    torch.cuda.synchronize()
+    prob = oracle_problem(w, pb)
+    s_ref, chi2_ref = adjoint.wf_forward(prob, pk / w.cell_volume, k)
+    loss_ref, gp_ref, gd_ref = adjoint.wf_gradient(prob, pk / w.cell_volume, k)
+    gp_ref = gp_ref / w.cell_volume           # per unit of physical P
+    e_s = float(np.abs(s_k.cpu().numpy() - s_ref).max() / np.sqrt(np.mean(s_ref ** 2)))
+    e_c = abs(float(chi2) - chi2_ref) / abs(chi2_ref)
+    e_gd = _rel(grad_d.cpu().numpy(), gd_ref)
+    e_gp = _rel(grad_pk.cpu().numpy(), gp_ref)
+    print(f"  err s={e_s:.2e} chi2={e_c:.2e} grad_d={e_gd:.2e} grad_P={e_gp:.2e}", flush=True)
+    tol = TOL[precision]
+    assert e_s < tol and e_c < tol and e_gd < tol and e_gp < tol
+    assert np.all(grad_d.cpu().numpy()[~pb["observed"]] == 0.0)
+
+
+def test_gradient_matches_gpu_central_differences():
+    import torch
+    k, every = 15, 4
+    w, pb, smp, d, pk, pk_t = _setup(32, 8, "fp64")
+    wf = binding.WienerFilter(smp, k, every)
+    wf.forward(d, pk_t)
+    grad_d, grad_pk = wf.backward(d)
+    gp, gd = grad_pk.cpu().numpy(), grad_d.cpu().numpy()
+    for b in range(w.n_bins):
+        h = 1e-3 * pk[b]
+        up, dn = pk_t.clone(), pk_t.clone()
+        up[b] += h
+        dn[b] -= h
+        fd = (float(wf.forward(d, up)[0]) - float(wf.forward(d, dn)[0])) / (2 * h)
+        print(f"  bin {b}: adjoint {gp[b]:.10e} fd {fd:.10e}", flush=True)
+        assert gp[b] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(gp).max())
+    rng = np.random.default_rng(1)
+    obs = np.flatnonzero(pb["observed"].ravel())
+    h = 1e-3 * float(np.sqrt(np.mean(pb["data"][pb["observed"]] ** 2)))
+    for i in rng.choice(obs, 6, replace=False):
+        up, dn = d.clone().view(-1), d.clone().view(-1)
+        up[i] += h
+        dn[i] -= h
+        fd = (float(wf.forward(up.view_as(d), pk_t)[0]) -
+              float(wf.forward(dn.view_as(d), pk_t)[0])) / (2 * h)
+        assert gd.ravel()[i] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(gd).max())
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    k = 9
+    w, pb, smp, d, pk, pk_t = _setup(32, 8, "fp32", seed=5)
+    out = []
+    for every in (1, 4, 9):
+        wf = binding.WienerFilter(smp, k, every)
+        chi2, _ = wf.forward(d, pk_t)
+        gd, gp = wf.backward(d)
+        out.append((float(chi2), gd.cpu().numpy(), gp.cpu().numpy()))
+    for c, gd, gp in out[1:]:
+        assert c == out[0][0]
+        assert np.array_equal(gd, out[0][1]) and np.array_equal(gp, out[0][2])
+
+
+def test_autograd_function_and_recompute():
+    import torch
+    from paper_1402_1763_amd.autograd import wiener_chi2
+    k, every = 6, 3
+    w, pb, smp, d, pk, pk_t = _setup(32, 8, "fp64", seed=8)
+    wf = binding.WienerFilter(smp, k, every)
+    pk1 = pk_t.clone().requires_grad_(True)
+    d1 = d.clone().requires_grad_(True)
+    loss1 = wiener_chi2(pk1, d1, wf)
+    loss2 = wiener_chi2(pk_t * 2.0, d, wf)      # overwrites the checkpoints
+    (3.0 * loss1).backward()
+    wf.forward(d, pk_t)
+    gd, gp = wf.backward(d)
+    assert torch.allclose(pk1.grad, 3.0 * gp, rtol=1e-12, atol=0)
+    assert torch.allclose(d1.grad, 3.0 * gd, rtol=1e-12, atol=0)
+    assert float(loss2) != float(loss1)
+
+
+def test_chain_state_is_untouched_and_errors():
+    import torch
+    w, pb, smp, d, pk, pk_t = _setup(32, 8, "fp32", seed=12)
+    smp.sweep(2)
+    s0, p0, n0 = smp.state()
+    wf = binding.WienerFilter(smp, 5, 2)
+    with pytest.raises(binding.MFError) as e:     # no forward run yet
+        wf.backward(d)
+    assert e.value.status == binding.MF_E_STATE
+    wf.forward(d, pk_t)
+    wf.backward(d)
+    torch.cuda.synchronize()
+    s1, p1, n1 = smp.state()
+    assert np.array_equal(s0, s1) and np.array_equal(p0, p1) and n0 == n1
+    smp.sweep(1)       # the chain continues as if no Wiener call happened
+    ref = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], 8, w.box, seed=w.rng_seed,
+                          precision="fp32", sample_pk=False)
+    ref.sweep(3)
+    assert np.array_equal(smp.state()[0], ref.state()[0])
+
+
+def test_unsupported_size_is_rejected():
+    import torch
+    w = workloads.small_workload(16, 4, precision="fp32")
+    pb = workloads.make_problem(w)
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], 4, w.box, seed=1,
+                          precision="fp32")
+    wf = binding.WienerFilter(smp, 4, 2)
+    with pytest.raises(binding.MFError) as e:
+        wf.forward(torch.from_numpy(pb["data"]).cuda(), torch.from_numpy(pb["pk_init"]).cuda())
+    assert e.value.status == binding.MF_E_UNSUPPORTED_SIZE
+
+
+def test_full_size_128_survey_50_iterations():
+    """The 128^3 survey problem, 32 bins, 50 iterations, checkpoint every 10
+    (FP32) against the FP64 oracle."""
+    import torch
+    w = workloads.SURVEY_128_FP32
+    pb = workloads.make_problem(w)
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision="fp32", sample_pk=False)
+    pk = workloads.power_spectrum(workloads.bin_centres(w), w)
+    d = torch.from_numpy(pb["data"]).cuda()
+    wf = binding.WienerFilter(smp, 50, 10)
+    print("wiener 128^3 survey K=50 E=10", flush=True)
+    chi2, _ = wf.forward(d, torch.from_numpy(pk).cuda())
+    gd, gp = wf.backward(d)
+    torch.cuda.synchronize()
+    prob = oracle_problem(w, pb)
+    loss_ref, gp_ref, gd_ref = adjoint.wf_gradient(prob, pk / w.cell_volume, 50)
+    e_c = abs(float(chi2) - loss_ref) / abs(loss_ref)
+    e_gd = _rel(gd.cpu().numpy(), gd_ref)
+    e_gp = _rel(gp.cpu().numpy(), gp_ref / w.cell_volume)
+    print(f"  err chi2={e_c:.2e} grad_d={e_gd:.2e} grad_P={e_gp:.2e}", flush=True)
+    assert e_c < TOL["fp32"] and e_gd < TOL["fp32"] and e_gp < TOL["fp32"]
