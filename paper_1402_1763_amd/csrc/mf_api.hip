@@ -242,7 +242,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
   using XS = mf::XSTile<R, N>;
   constexpr bool split = mf::split_x<N>();
   const dim3 zgrid(N / ZT::P, N / ZT::IXB, nch), zgrid1(N / ZT::P, N / ZT::IXB, 1);
-  const size_t tables = 2 * a.nb * sizeof(R) + a.nb * 4;
+  const size_t tables = 2 * a.nb * sizeof(R) + (a.nb + 1) * 4;
   switch (id) {
     case kZ:
       hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZSweep>), zgrid, dim3(ZT::NT), 0, st, a);

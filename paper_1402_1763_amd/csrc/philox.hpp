@@ -46,7 +46,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 
 template <typename R>
 __device__ __forceinline__ R u23(uint32_t x) {
-  return (static_cast<R>(x >> 9) + R(0.5)) * R(1.1920928955078125e-07);  // 2^-23
+  // (floor(x / 2^9) + 1/2) 2^-23 as one fused multiply-add: both forms are
+  // exact (at most 24 significant bits), so they agree bit for bit
+  return fma(static_cast<R>(x >> 9), R(1.1920928955078125e-07), R(5.9604644775390625e-08));
 }
 
 // Box-Muller pair from two words, in the precision R.  The FP32 form uses the

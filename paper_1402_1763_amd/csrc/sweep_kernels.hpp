@@ -587,13 +587,16 @@ ysplit_kernel(SweepArgs<R> a) {
 // ---------------------------------------------------------------- x-pass
 __device__ __forceinline__ int wavenumber(int i, int n) { return i <= n / 2 ? i : i - n; }
 
-// Bin of q >= 1: the largest b with Q_b <= q (thresholds Q_b in LDS).
+// Bin of q >= 1: the largest b with Q_b <= q.  qthr (LDS) holds the nb
+// thresholds Q_b and a sentinel INT32_MAX at index nb.  The float estimate
+// floor(sqrt(q * qscale)), qscale = 4 nb^2 / (3 N^2), is the exact bin up to
+// rounding, i.e. off by at most one either way; one comparison against each
+// neighbouring threshold (read together) corrects it.
 __device__ __forceinline__ int bin_of(int q, const int32_t* qthr, int nb, float qscale) {
   int b = static_cast<int>(__builtin_amdgcn_sqrtf(static_cast<float>(q) * qscale));
-  b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
-  if (b + 1 < nb && q >= qthr[b + 1]) ++b;
-  if (b > 0 && q < qthr[b]) --b;
-  return b;
+  b = b > nb - 1 ? nb - 1 : b;
+  const int lo = qthr[b], hi = qthr[b + 1];
+  return b + (q >= hi ? 1 : 0) - (q < lo ? 1 : 0);
 }
 
 template <typename R>
@@ -612,26 +615,57 @@ struct DrawCtx {
 // conditional
 //   s^ = f t^ + sqrt(v/2) (G_re + i G_im),  f = P/(P + tau), v = M tau f,
 // stored divided by M: s^/M = A_b t^ + B_b (G_re + i G_im), A_b = f/M,
-// B_b = sqrt(tau f / (2M)).  Self-conjugate modes are real with the full
-// variance; on the kz = 0 and kz = N/2 planes the member of a conjugate pair
-// with the larger ix*N + iy uses its partner's normals conjugated; q = 0
-// gives 0.  (G_re, G_im) of (ix, iy, kz) come from Philox counter
-// ((kz N + iy) N/2 + ix mod N/2, sweep, 1, chain): words (x0, x1) for
-// ix < N/2, (x2, x3) for ix >= N/2 -- modes r and r + RL/2 share a call.
-// w |s^/M|^2 (w = 1 on kz = 0, N/2, else 2) is added to the lane's LDS
-// histogram.
+// B_b = sqrt(tau f / (2M)).  (G_re, G_im) of (ix, iy, kz) come from Philox
+// counter ((kz N + iy) N/2 + ix mod N/2, sweep, 1, chain): words (x0, x1)
+// for ix < N/2, (x2, x3) for ix >= N/2 -- modes r and r + RL/2 share a call.
+// |s^/M|^2 (squared in R) is added to the lane's LDS histogram; the weight
+// w of the plane (1 on kz = 0, N/2, else 2) is applied per workgroup in
+// draw_epilogue.  This is the form for planes 0 < kz < N/2, where every
+// mode is drawn independently and q >= 1.
 template <typename R, int N, int RL, int S>
-__device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
-                                          const SweepArgs<R>& a, const DrawCtx<R>& d) {
+__device__ __forceinline__ void draw_slot_plain(cx<R>* v, int q, int iy, int kz,
+                                                const SweepArgs<R>& a, const DrawCtx<R>& d) {
   constexpr int H = N / 2;
-  const bool herm = (kz == 0 || kz == H);
-  const double wgt = herm ? 1.0 : 2.0;
+  const int my = wavenumber(iy, N);
+  const int r2 = my * my + kz * kz;
+#pragma unroll
+  for (int r = 0; r < RL / 2; ++r) {
+    const int ixl = q + S * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
+    R g[4];
+    {
+      const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
+      const Words4 w = philox4x32_10(w0, d.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
+      box_muller(w.x0, w.x1, g[0], g[1]);
+      box_muller(w.x2, w.x3, g[2], g[3]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = r + h * (RL / 2);
+      const int mx = wavenumber(ixl + h * H, N);
+      const int b = bin_of(mx * mx + r2, d.qthr, d.nb, d.qscale);
+      const cx<R> ab = d.tab[b];
+      const cx<R> t = v[e];
+      const cx<R> out{ab.x * t.x + ab.y * g[2 * h], ab.x * t.y + ab.y * g[2 * h + 1]};
+      atomicAdd(d.hist + b, static_cast<double>(out.x * out.x + out.y * out.y));
+      v[e] = out;
+    }
+  }
+}
+
+// The same on the kz = 0 and kz = N/2 planes, where s^ is Hermitian within
+// the plane: self-conjugate modes are real with the full variance; the member
+// of a conjugate pair with the larger ix*N + iy uses its partner's normals
+// conjugated; q = 0 gives 0.
+template <typename R, int N, int RL, int S>
+__device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
+                                               const SweepArgs<R>& a, const DrawCtx<R>& d) {
+  constexpr int H = N / 2;
   const int my = wavenumber(iy, N);
   const int r2 = my * my + kz * kz;
   const int py = (N - iy) % N;
 #pragma unroll
   for (int r = 0; r < RL / 2; ++r) {
-    const int ixl = q + S * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
+    const int ixl = q + S * r;
     R g[4];
     {
       const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
@@ -646,55 +680,57 @@ __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
       const int mx = wavenumber(x, N);
       const int qq = mx * mx + r2;
       const int plin = ((N - x) % N) * N + py, lin = x * N + iy;
-      if (herm && plin < lin) continue;   // drawn in the second loop
+      if (plin < lin) continue;   // drawn in the second loop
       cx<R> out{R(0), R(0)};
       if (qq > 0) {
         const int b = bin_of(qq, d.qthr, d.nb, d.qscale);
         const cx<R> ab = d.tab[b];
         const cx<R> t = v[e];
-        if (herm && plin == lin)   // self-conjugate: real, full variance
+        if (plin == lin)   // self-conjugate: real, full variance
           out = cx<R>{ab.x * t.x + R(1.4142135623730950488) * ab.y * g[2 * h], R(0)};
         else
           out = cx<R>{ab.x * t.x + ab.y * g[2 * h], ab.x * t.y + ab.y * g[2 * h + 1]};
-        const double ox = static_cast<double>(out.x), oy = static_cast<double>(out.y);
-        atomicAdd(d.hist + b, wgt * (ox * ox + oy * oy));
+        atomicAdd(d.hist + b, static_cast<double>(out.x * out.x + out.y * out.y));
       }
       v[e] = out;
     }
   }
-  if (herm) {
 #pragma unroll
-    for (int e = 0; e < RL; ++e) {
-      const int x = q + S * e;
-      const int px = (N - x) % N;
-      if (px * N + py >= x * N + iy) continue;
-      const int mx = wavenumber(x, N);
-      const int b = bin_of(mx * mx + r2, d.qthr, d.nb, d.qscale);
-      const cx<R> ab = d.tab[b];
-      const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px % H));
-      const Words4 w = philox4x32_10(w0, d.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
-      R g0, g1;
-      if (px >= H) box_muller(w.x2, w.x3, g0, g1);
-      else box_muller(w.x0, w.x1, g0, g1);
-      const cx<R> t = v[e];
-      const cx<R> out{ab.x * t.x + ab.y * g0, ab.x * t.y - ab.y * g1};
-      const double ox = static_cast<double>(out.x), oy = static_cast<double>(out.y);
-      atomicAdd(d.hist + b, wgt * (ox * ox + oy * oy));
-      v[e] = out;
-    }
+  for (int e = 0; e < RL; ++e) {
+    const int x = q + S * e;
+    const int px = (N - x) % N;
+    if (px * N + py >= x * N + iy) continue;
+    const int mx = wavenumber(x, N);
+    const int b = bin_of(mx * mx + r2, d.qthr, d.nb, d.qscale);
+    const cx<R> ab = d.tab[b];
+    const uint32_t w0 = static_cast<uint32_t>((kz * N + py) * H + (px % H));
+    const Words4 w = philox4x32_10(w0, d.sweep, kPhaseSignal, d.chain, a.key0, a.key1);
+    R g0, g1;
+    if (px >= H) box_muller(w.x2, w.x3, g0, g1);
+    else box_muller(w.x0, w.x1, g0, g1);
+    const cx<R> t = v[e];
+    const cx<R> out{ab.x * t.x + ab.y * g0, ab.x * t.y - ab.y * g1};
+    atomicAdd(d.hist + b, static_cast<double>(out.x * out.x + out.y * out.y));
+    v[e] = out;
   }
+}
+
+template <typename R, int N, int RL, int S>
+__device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
+                                          const SweepArgs<R>& a, const DrawCtx<R>& d) {
+  if (kz == 0 || kz == N / 2) draw_slot_herm<R, N, RL, S>(v, q, iy, kz, a, d);
+  else draw_slot_plain<R, N, RL, S>(v, q, iy, kz, a, d);
 }
 
 // Deterministic counterpart of draw_slot for the Wiener iteration: every mode
 // becomes A_b t^ (the signal conditional's mean, f_b t^ / M).  XM = kXDet
-// stores t^ to aux (when set); XM = kXAdj adds w Re(conj(t^) u^) / 1 to the
-// bin's histogram, u^ read from aux -- the per-bin sum of the adjoint's
-// d chi2 / d f_b (before its 1/M).  aux element e sits at aux[e * astride].
+// stores t^ to aux (when set); XM = kXAdj adds Re(conj(t^) u^) to the bin's
+// histogram, u^ read from aux -- with the plane weight w applied in
+// draw_epilogue, the per-bin sum of the adjoint's d chi2 / d f_b (before its
+// 1/M).  aux element e sits at aux[e * astride].
 template <typename R, int N, int RL, int S, int XM>
 __device__ __forceinline__ void filter_slot(cx<R>* v, int q, int iy, int kz, const DrawCtx<R>& d,
                                             cx<R>* aux, size_t astride) {
-  constexpr int H = N / 2;
-  const double wgt = (kz == 0 || kz == H) ? 1.0 : 2.0;
   const int my = wavenumber(iy, N);
   const int r2 = my * my + kz * kz;
 #pragma unroll
@@ -709,8 +745,7 @@ __device__ __forceinline__ void filter_slot(cx<R>* v, int q, int iy, int kz, con
       out = cx<R>{f * t.x, f * t.y};
       if (XM == kXAdj) {
         const cx<R> u = aux[e * astride];
-        atomicAdd(d.hist + b, wgt * (static_cast<double>(t.x) * u.x +
-                                     static_cast<double>(t.y) * u.y));
+        atomicAdd(d.hist + b, static_cast<double>(t.x) * u.x + static_cast<double>(t.y) * u.y);
       }
     }
     if (XM == kXDet && aux != nullptr) aux[e * astride] = t;
@@ -729,7 +764,7 @@ __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c
   int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * nb);
   for (int i = tid; i < NHIST * nb; i += NT) hist[i] = 0.0;
   for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
-  for (int i = tid; i < nb; i += NT) qthr[i] = a.qthr[i];
+  for (int i = tid; i <= nb; i += NT) qthr[i] = i < nb ? a.qthr[i] : INT32_MAX;
   DrawCtx<R> d;
   d.qthr = qthr;
   d.tab = reinterpret_cast<const cx<R>*>(tab);
@@ -741,8 +776,12 @@ __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c
   return d;
 }
 
+// The workgroup's plane kz sets the weight w of its modes in the full-grid
+// sums: 1 on kz = 0 and kz = N/2, 2 elsewhere (each mode stands for itself
+// and its conjugate).
 template <typename R, int NT, int NHIST>
-__device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, double* hist, int wg) {
+__device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, double* hist, int wg,
+                                              double wgt) {
   __syncthreads();   // all histogram atomics are done
   const int nb = a.nb, tid = threadIdx.x;
   double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
@@ -766,7 +805,7 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
   for (int b = tid; b < nb; b += NT) {
     double s = 0.0;
     for (int g = 0; g < COUNT; ++g) s += hist[g * STEP * nb + b];
-    part[static_cast<size_t>(b) * a.n_wg_x] = s;
+    part[static_cast<size_t>(b) * a.n_wg_x] = wgt * s;
   }
 }
 
@@ -788,7 +827,7 @@ __global__ void __launch_bounds__((XSTile<R, N>::NT))
 xsplit_kernel(SweepArgs<R> a) {
   using T = XSTile<R, N>;
   constexpr int P = T::P, NT = T::NT, NA = T::NA;
-  extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb)
+  extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb + 1)
   const int tid = threadIdx.x;
   const int iy0 = blockIdx.x * P;
   const int kz = blockIdx.y;
@@ -811,7 +850,9 @@ xsplit_kernel(SweepArgs<R> a) {
   dft<R, 16, true>(v);
 #pragma unroll
   for (int j = 0; j < 16; ++j) base[static_cast<size_t>(j) * N] = v[j];
-  if (XM != kXDet) draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x);
+  if (XM != kXDet)
+    draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x,
+                                   (kz == 0 || kz == N / 2) ? 1.0 : 2.0);
 }
 
 // Whole-transform x-pass (N = 8, 16, 512): workgroup = one kz plane and P
@@ -859,7 +900,8 @@ xpass_kernel(SweepArgs<R> a) {
     TL::template out_pos<true>(tid, e, col, ix);
     spec[static_cast<size_t>(ix) * N + iy0 + col] = v[e];
   }
-  draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x);
+  draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x,
+                                 (kz == 0 || kz == N / 2) ? 1.0 : 2.0);
 }
 
 }  // namespace mf
