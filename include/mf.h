@@ -229,6 +229,47 @@ mf_status mf_wiener_forward(mf_problem* p, int32_t chain, const double* d, const
 mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void* workspace,
                              size_t ws_bytes, double* grad_d, double* grad_pk, void* stream);
 
+/* Chain diagnostics (Sec. 4.3).
+ *
+ * Recording.  mf_set_diagnostics makes sweeps record sample n, the chain
+ * state after n sweeps, as sweep n begins, for n = start + j * thin
+ * (j = 0, 1, ...).  Two kinds of record can be kept, each optional (NULL
+ * switches it off):
+ *  - trace: caller-owned device FP64 array [n_chains][trace_cap][n_bins].
+ *    Entry j holds P_b of recorded sample j in physical units; recording
+ *    stops after trace_cap samples.
+ *  - moments: caller-owned device FP64 array of n_chains * 2 * N^3 doubles,
+ *    in the library's own order.  It holds running (Welford) sums for the
+ *    posterior mean and variance of s.  It is zeroed here, and the z-pass
+ *    updates it on every recorded sweep.
+ * Sizes are given by mf_diagnostics_bytes.  The settings apply to sweeps
+ * enqueued afterwards and to graphs created afterwards.  Calling again
+ * resets the recording, and both NULL stops it.  Errors: MF_E_INVALID_ARG
+ * (thin < 1, start >= 2^32, unaligned buffers).
+ * mf_recorded_samples: samples recorded so far, from the problem's sweep
+ * count (the trace holds min(count, trace_cap) of them).
+ * mf_get_moments: writes the posterior mean and variance (population form,
+ * 1/K over the K recorded samples) of chain `chain` to the device FP64
+ * arrays mean and var (N^3 each, [ix][iy][iz]).  Enqueued on `stream`.
+ * MF_E_STATE without a moment buffer or before the first recorded sample.
+ *
+ * Autocorrelation.  mf_acf takes a device FP64 trace [t][n_bins] (one
+ * chain's records).  It writes the autocorrelation
+ *   acf[n][b] = sum_{i < t-n} (x_i - mu)(x_{i+n} - mu) / ((t - n) var)
+ * for n = 0 .. max_lag (Eq. CORR_COEFF: mean and variance taken over the t
+ * samples, the average over the t - n available pairs), and the correlation
+ * length nc[b], the first lag with acf < 0.1 or -1 if there is none
+ * (device int32, n_bins).  A constant series gives NaN.  Enqueued on
+ * `stream`.  MF_E_INVALID_ARG unless t >= 2 and 0 <= max_lag < t. */
+mf_status mf_diagnostics_bytes(const mf_problem* p, int32_t trace_cap, size_t* trace_bytes,
+                               size_t* moments_bytes);
+mf_status mf_set_diagnostics(mf_problem* p, uint64_t start, int32_t thin, double* trace,
+                             int32_t trace_cap, double* moments, void* stream);
+mf_status mf_recorded_samples(const mf_problem* p, uint64_t* count);
+mf_status mf_get_moments(mf_problem* p, int32_t chain, double* mean, double* var, void* stream);
+mf_status mf_acf(const double* trace, int32_t t, int32_t n_bins, int32_t max_lag, double* acf,
+                 int32_t* nc, void* stream);
+
 /* Release the handle (not the workspace).  NULL is ignored. */
 void mf_destroy_problem(mf_problem* p);
 

@@ -88,6 +88,17 @@ SIGNATURES = {
     "mf_wiener_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "mf_diagnostics_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_size_t),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_set_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "mf_recorded_samples": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "mf_get_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "mf_acf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mf_destroy_problem": (None, [ctypes.c_void_p]),
     "mf_last_error": (ctypes.c_char_p, []),
 }
@@ -360,6 +371,49 @@ class Sampler:
     def load_checkpoint(self, data: bytes, chain: int = 0):
         mf_load_checkpoint(self.handle, chain, data, self.stream.cuda_stream)
 
+    def set_diagnostics(self, start: int = 0, thin: int = 1, trace_cap: int = 0,
+                        moments: bool = False):
+        """Record samples start, start + thin, ...: P traces (trace_cap
+        samples per chain) and/or Welford moments of s, in torch-owned device
+        buffers."""
+        import torch
+        tb, mb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(load().mf_diagnostics_bytes(ctypes.c_void_p(self.handle), trace_cap,
+                                           ctypes.byref(tb), ctypes.byref(mb)))
+        dev = self.workspace.device
+        self.trace_buf = (torch.zeros(self.n_chains, trace_cap, self.n_bins, dtype=torch.float64,
+                                      device=dev) if trace_cap > 0 else None)
+        self.moment_buf = (torch.empty(mb.value // 8, dtype=torch.float64, device=dev)
+                           if moments else None)
+        _check(load().mf_set_diagnostics(
+            ctypes.c_void_p(self.handle), start, thin,
+            ctypes.c_void_p(self.trace_buf.data_ptr() if self.trace_buf is not None else None),
+            trace_cap,
+            ctypes.c_void_p(self.moment_buf.data_ptr() if self.moment_buf is not None else None),
+            ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def recorded(self) -> int:
+        out = ctypes.c_uint64(0)
+        _check(load().mf_recorded_samples(ctypes.c_void_p(self.handle), ctypes.byref(out)))
+        return out.value
+
+    def trace(self, chain: int = 0):
+        """Recorded P_b samples of a chain, a (count, n_bins) float64 cuda tensor."""
+        k = min(self.recorded(), self.trace_buf.shape[1])
+        return self.trace_buf[chain, :k]
+
+    def moments(self, chain: int = 0):
+        """(mean, variance) of the recorded s samples as (N, N, N) float64 cuda tensors."""
+        import torch
+        n = self.n
+        mean = torch.empty((n, n, n), dtype=torch.float64, device=self.workspace.device)
+        var = torch.empty_like(mean)
+        _check(load().mf_get_moments(ctypes.c_void_p(self.handle), chain,
+                                     ctypes.c_void_p(mean.data_ptr()),
+                                     ctypes.c_void_p(var.data_ptr()),
+                                     ctypes.c_void_p(self.stream.cuda_stream)))
+        return mean, var
+
     def close(self):
         if getattr(self, "handle", None):
             mf_destroy_problem(self.handle)
@@ -443,3 +497,18 @@ class WienerFilter:
                            self.ws_bytes, grad_d.data_ptr(), grad_pk.data_ptr(),
                            self.sampler.stream.cuda_stream)
         return grad_d, grad_pk
+
+
+def acf(trace, max_lag: int, stream=None):
+    """Autocorrelation C_n (n <= max_lag) and correlation length of every
+    column of a (T, n_bins) float64 cuda tensor (Eq. CORR_COEFF, ten-percent
+    rule); returns (acf (max_lag + 1, n_bins), nc (n_bins,) int32)."""
+    import torch
+    trace = trace.contiguous()
+    t, nb = trace.shape
+    out = torch.empty((max_lag + 1, nb), dtype=torch.float64, device=trace.device)
+    nc = torch.empty(nb, dtype=torch.int32, device=trace.device)
+    _check(load().mf_acf(ctypes.c_void_p(trace.data_ptr()), t, nb, max_lag,
+                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(nc.data_ptr()),
+                         ctypes.c_void_p(_stream_ptr(stream))))
+    return out, nc

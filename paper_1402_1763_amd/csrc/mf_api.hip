@@ -183,6 +183,14 @@ struct WienerRun {
   int chain = -1, n_iter = 0, every = 0;
 };
 
+// Recording of samples for the chain diagnostics (caller-owned buffers).
+struct DiagRec {
+  double* trace = nullptr;    // [chain][cap][nb]
+  double* mom = nullptr;      // [chain][2][m]
+  uint64_t start = 0;
+  int thin = 0, cap = 0;
+};
+
 struct mf_problem {
   mf_chain_desc desc;
   Layout L;
@@ -191,6 +199,7 @@ struct mf_problem {
   std::vector<double> tau;
   uint64_t sweep;
   WienerRun wiener;
+  DiagRec diag;
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
 
@@ -225,6 +234,12 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   a.cb = R(1);
   a.advance = 1;
   a.pk_mode = mf::kPkDraw;
+  a.trace = p->diag.trace;
+  a.mom = p->diag.mom;
+  a.diag_start = static_cast<uint32_t>(p->diag.start);
+  a.diag_thin = p->diag.thin;
+  a.trace_cap = p->diag.cap;
+  a.vcell = std::pow(p->desc.box / p->desc.n, 3);
   return a;
 }
 
@@ -1083,6 +1098,102 @@ mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void
   char* g = static_cast<char*>(workspace);
   return p->fp64() ? wiener_backward<double>(p, chain, d, g, W, grad_d, grad_pk, hs)
                    : wiener_backward<float>(p, chain, d, g, W, grad_d, grad_pk, hs);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- diagnostics
+namespace {
+
+// Samples n in [start, sweep) with (n - start) % thin == 0.
+uint64_t recorded_count(const mf_problem* p) {
+  const DiagRec& d = p->diag;
+  if (d.thin <= 0 || p->sweep <= d.start) return 0;
+  return (p->sweep - d.start - 1) / static_cast<uint64_t>(d.thin) + 1;
+}
+
+template <typename R>
+void launch_moments(const mf_problem* p, int chain, double count, double* mean, double* var,
+                    hipStream_t st) {
+  const int n = p->desc.n;
+  const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
+  const double* mom = p->diag.mom + static_cast<size_t>(chain) * 2 * m;
+  const int nblk = static_cast<int>((entries + mf::kWienerThreads - 1) / mf::kWienerThreads);
+  auto go = [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL((mf::moments_kernel<R, N>), dim3(nblk), dim3(mf::kWienerThreads), 0, st, mom,
+                       count, mean, var, entries);
+  };
+  switch (n) {
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 16: go(std::integral_constant<int, 16>{}); break;
+    case 512: go(std::integral_constant<int, 512>{}); break;
+    default: with_n(n, go); break;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_diagnostics_bytes(const mf_problem* p, int32_t trace_cap, size_t* trace_bytes,
+                               size_t* moments_bytes) {
+  if (!p || !trace_bytes || !moments_bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (trace_cap < 0) return fail(MF_E_INVALID_ARG, "negative trace capacity");
+  const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  *trace_bytes = static_cast<size_t>(p->desc.n_chains) * trace_cap * p->desc.n_bins * 8;
+  *moments_bytes = static_cast<size_t>(p->desc.n_chains) * 2 * m * 8;
+  return MF_OK;
+}
+
+mf_status mf_set_diagnostics(mf_problem* p, uint64_t start, int32_t thin, double* trace,
+                             int32_t trace_cap, double* moments, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (thin < 1) return fail(MF_E_INVALID_ARG, "thin must be >= 1");
+  if (trace && trace_cap < 1) return fail(MF_E_INVALID_ARG, "trace capacity must be >= 1");
+  if (start > 0xffffffffull) return fail(MF_E_INVALID_ARG, "start sweep beyond 2^32 - 1");
+  for (const void* q : {static_cast<const void*>(trace), static_cast<const void*>(moments)})
+    if (q && reinterpret_cast<uintptr_t>(q) % 8 != 0)
+      return fail(MF_E_INVALID_ARG, "diagnostic buffers must be 8-byte aligned");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (moments) {
+    const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+    hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1024), dim3(256), 0, hs, moments,
+                       static_cast<size_t>(p->desc.n_chains) * 2 * m);
+    const mf_status r = check_launch("moment buffer clear");
+    if (r != MF_OK) return r;
+  }
+  p->diag = DiagRec{trace, moments, start, thin, trace ? trace_cap : 0};
+  if (!trace && !moments) p->diag = DiagRec{};
+  return MF_OK;
+}
+
+mf_status mf_recorded_samples(const mf_problem* p, uint64_t* count) {
+  if (!p || !count) return fail(MF_E_INVALID_ARG, "NULL argument");
+  *count = recorded_count(p);
+  return MF_OK;
+}
+
+mf_status mf_get_moments(mf_problem* p, int32_t chain, double* mean, double* var, void* stream) {
+  if (!p || !mean || !var) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  if (!p->diag.mom) return fail(MF_E_STATE, "no moment buffer set (mf_set_diagnostics)");
+  const uint64_t k = recorded_count(p);
+  if (k == 0) return fail(MF_E_STATE, "no sample recorded yet");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (p->fp64()) launch_moments<double>(p, chain, static_cast<double>(k), mean, var, hs);
+  else launch_moments<float>(p, chain, static_cast<double>(k), mean, var, hs);
+  return check_launch("moments");
+}
+
+mf_status mf_acf(const double* trace, int32_t t, int32_t n_bins, int32_t max_lag, double* acf,
+                 int32_t* nc, void* stream) {
+  if (!trace || !acf || !nc) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (t < 2 || n_bins < 1 || max_lag < 0 || max_lag >= t)
+    return fail(MF_E_INVALID_ARG, "need t >= 2, n_bins >= 1 and 0 <= max_lag < t");
+  hipLaunchKernelGGL(mf::acf_kernel, dim3(n_bins), dim3(mf::kWienerThreads), 0,
+                     static_cast<hipStream_t>(stream), trace, t, n_bins, max_lag, acf, nc);
+  return check_launch("acf");
 }
 
 }  // extern "C"

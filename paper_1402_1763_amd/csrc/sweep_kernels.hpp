@@ -59,7 +59,23 @@ struct SweepArgs {
   double* gacc;           // [chain][nb] accumulated d chi2 / d f_b
   int32_t advance;        // the forward y-pass advances the sweep counter
   int32_t pk_mode;        // P(k) workgroups of the inverse y-pass (PkMode)
+  // Diagnostics: sample n (the state after n sweeps) is recorded as sweep n
+  // begins, for n = diag_start + j diag_thin, j >= 0.
+  double* trace;          // [chain][trace_cap][nb] P_b of sample n, physical units
+  double* mom;            // [chain][2][m] Welford mean and M2 of s, z-pass order
+  uint32_t diag_start;
+  int32_t diag_thin;
+  int32_t trace_cap;
+  double vcell;
 };
+
+// Index j of sample `sweep` among the recorded ones, or -1.
+template <typename R>
+__device__ __forceinline__ int recorded(const SweepArgs<R>& a, uint32_t sweep) {
+  if (a.diag_thin <= 0 || sweep < a.diag_start) return -1;
+  const uint32_t d = sweep - a.diag_start;
+  return d % static_cast<uint32_t>(a.diag_thin) == 0 ? static_cast<int>(d / a.diag_thin) : -1;
+}
 
 enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2, kZDet = 3, kZAccum = 4 };
 enum XMode : int { kXSample = 0, kXDet = 1, kXAdj = 2 };
@@ -232,6 +248,26 @@ zpass_kernel(SweepArgs<R> a) {
       else v[e] = cx<R>{A.x + B.y, B.x - A.y};
     }
     fft_regs<R, N, TL, NT, true, false>(v, lds, tw);
+    if (MODE == kZSweep && a.mom != nullptr) {
+      const int j = recorded(a, sweep);
+      if (j >= 0) {   // Welford update with the (j + 1)-th sample
+        const double inv_k = 1.0 / (j + 1.0);
+        double* mean = a.mom + static_cast<size_t>(c) * 2 * a.m +
+                       static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 2;
+        double* m2 = mean + a.m;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const size_t i = (static_cast<size_t>(e) * NT + tid) * 2;
+          const double x0 = v[e].x, x1 = v[e].y;
+          const double u0 = mean[i], u1 = mean[i + 1];
+          const double n0 = u0 + (x0 - u0) * inv_k, n1 = u1 + (x1 - u1) * inv_k;
+          mean[i] = n0;
+          mean[i + 1] = n1;
+          m2[i] += (x0 - u0) * (x0 - n0);
+          m2[i + 1] += (x1 - u1) * (x1 - n1);
+        }
+      }
+    }
     if (MODE == kZAccum || (MODE == kZDet && a.acc != nullptr)) {
       R* acc = a.acc + static_cast<size_t>(c) * a.m +
                static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 2;
@@ -379,6 +415,11 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
     const double tau = a.tau[c];
     double* pk = a.pk + static_cast<size_t>(c) * a.nb;
     double p = pk[b];
+    if (a.trace != nullptr) {
+      const int j = recorded(a, a.ctr[1]);
+      if (j >= 0 && j < a.trace_cap)
+        a.trace[(static_cast<size_t>(c) * a.trace_cap + j) * a.nb + b] = p * a.vcell;
+    }
     if (a.sample_pk && a.counts[b] > 0.0) {
       const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.ctr[1],
                                 a.chain0 + c, a.key0, a.key1);

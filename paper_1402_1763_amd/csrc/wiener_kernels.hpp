@@ -146,4 +146,56 @@ __global__ void wiener_grad_pk_kernel(const double* gacc, const double* pkg, dou
   grad_pk[b] = gacc[b] * tau / (den * den) / vcell;
 }
 
+// ---------------------------------------------------------------- diagnostics
+// Posterior mean and variance (population form, M2 / K) of a chain's recorded
+// samples, from the z-pass-order Welford sums to [ix][iy][iz].
+template <typename R, int N>
+__global__ void __launch_bounds__(kWienerThreads)
+moments_kernel(const double* mom, double count, double* mean_out, double* var_out, size_t entries) {
+  const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
+  if (idx >= entries) return;
+  size_t va = 0, vb = 0;
+  entry_voxels<R, N>(idx, va, vb);
+  const double* m2 = mom + 2 * entries;
+  mean_out[va] = mom[idx * 2];
+  mean_out[vb] = mom[idx * 2 + 1];
+  var_out[va] = m2[idx * 2] / count;
+  var_out[vb] = m2[idx * 2 + 1] / count;
+}
+
+// Autocorrelation of a recorded chain (Sec. 4.3, Eq. CORR_COEFF), one
+// workgroup per bin b of trace [t][nb]: with mean mu and variance var over the
+// t samples, acf[n][b] = sum_{i < t-n} (x_i - mu)(x_{i+n} - mu) / ((t - n) var)
+// for n <= max_lag, and nc[b] = the first n with acf < 0.1 (-1 if none).  All
+// sums run in a fixed order.
+__global__ void __launch_bounds__(kWienerThreads)
+acf_kernel(const double* trace, int t, int nb, int max_lag, double* acf, int32_t* nc) {
+  __shared__ double red[kWienerThreads];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double x = 0.0;
+  for (int i = tid; i < t; i += kWienerThreads) x += trace[static_cast<size_t>(i) * nb + b];
+  const double mu = block_sum(red, x) / t;
+  __syncthreads();
+  x = 0.0;
+  for (int i = tid; i < t; i += kWienerThreads) {
+    const double dv = trace[static_cast<size_t>(i) * nb + b] - mu;
+    x += dv * dv;
+  }
+  const double var = block_sum(red, x) / t;
+  for (int n = tid; n <= max_lag; n += kWienerThreads) {
+    double sum = 0.0;
+    for (int i = 0; i + n < t; ++i)
+      sum += (trace[static_cast<size_t>(i) * nb + b] - mu) *
+             (trace[static_cast<size_t>(i + n) * nb + b] - mu);
+    acf[static_cast<size_t>(n) * nb + b] = sum / ((t - n) * var);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int first = -1;
+    for (int n = 0; n <= max_lag && first < 0; ++n)
+      if (acf[static_cast<size_t>(n) * nb + b] < 0.1) first = n;
+    nc[b] = first;
+  }
+}
+
 }  // namespace mf
