@@ -159,6 +159,44 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mixing(args):
+    """Mixing sweeps (Sec. 3.3, shell form) on the 256^3 survey problem."""
+    import torch
+
+    from paper_1402_1763_amd import binding, workloads
+    torch.cuda.set_device(0)
+    w = workloads.SURVEY_256_MIXED
+    pb = workloads.make_problem(w)
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision=w.precision)
+    stream = torch.cuda.current_stream()
+    smp.mixing_sweep(args.warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    smp.mixing_sweep(args.steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    _, pk, _ = smp.state(want_s=False)
+    assert np.all(np.isfinite(pk))
+    n = w.n
+    n_wg_x = (n // 2 + 1) * (n // x_columns(n))
+    spec = 8 * (n // 2 + 1) * n * n
+    nbytes = (sum(algorithmic_bytes(n, 4, w.n_bins, n_wg_x).values())
+              + 2 * spec + 2 * n_wg_x * w.n_bins * 8)        # rescaling pass, cross sums
+    out = {
+        "metric": "mixing sweeps/s at 256^3 FP32 (Alg. 3, shell form)",
+        "value": round(1000.0 / ms, 2), "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mixing-256^3-fp32-survey", "n": n, "n_bins": w.n_bins,
+                   "sweep_bytes_algorithmic": nbytes,
+                   "sweep_hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def wiener_grad_bytes(n: int, real_bytes: int, n_bins: int, n_iter: int, every: int) -> int:
     """Algorithmic HBM bytes of one chi2 forward + backward run of the
     messenger Wiener filter (K iterations, checkpoint every E): K plain
@@ -301,6 +339,8 @@ def main():
         return bench_batched(args)
     if args.workload == "wiener-grad-128^3-fp32-survey":
         return bench_wiener(args)
+    if args.workload == "mixing-256^3-fp32-survey":
+        return bench_mixing(args)
     w = workloads.WORKLOADS[args.workload]
     pb = workloads.make_problem(w)
     torch.cuda.set_device(0)

@@ -149,6 +149,21 @@ mf_status mf_save_checkpoint(mf_problem* p, int32_t chain, void* buf, size_t byt
 mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size_t bytes,
                              void* stream);
 
+/* Mixing sweeps (Sec. 3.3, Alg. 3, in the shell form), grid sides 32 to 256.
+ * One mixing sweep draws the messenger t | s, then updates (s^, P) jointly
+ * given t^ in the coordinates s^ = sqrt(S^) x^, S^_b = M P_b.  It draws x^
+ * (the signal conditional at the current P, divided by sqrt(S^)).  Then per
+ * bin it makes a Metropolis-Hastings move of U = sqrt(S^_b) with the
+ * truncated-normal independence proposal N(R_b/X_b, T^/X_b) | U > 0, where
+ * X_b = sum |x^|^2 and R_b = sum Re(conj(x^) t^) over the bin's modes.  The
+ * move is accepted with probability min(1, U/U'), the ratio that Jeffreys'
+ * prior gives.  Finally s^ = sqrt(S^') x^ and the inverse transform.  Draws
+ * use Philox phase 3 (counter (b 2^16 + attempt, sweep, 3, chain)) besides
+ * the messenger and signal phases.  Mixing and Gibbs sweeps may be
+ * interleaved freely; both advance the sweep index.  Enqueued on `stream`.
+ * Errors: MF_E_UNSUPPORTED_SIZE, MF_E_INVALID_ARG, MF_E_DEVICE. */
+mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
+
 /* The messenger variance tau of a chain (host value). */
 mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out);
 

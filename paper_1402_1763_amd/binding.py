@@ -58,6 +58,7 @@ SIGNATURES = {
                                        ctypes.c_size_t, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "mf_gibbs_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "mf_mixing_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mf_gibbs_sweep_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             _c_double_p, ctypes.c_int32]),
     "mf_get_chain_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
@@ -351,6 +352,11 @@ class Sampler:
 
     def sweep(self, n_sweeps: int = 1):
         mf_gibbs_sweep(self.handle, n_sweeps, self.stream.cuda_stream)
+
+    def mixing_sweep(self, n_sweeps: int = 1):
+        """Mixing sweeps (joint (s^, P) update given the messenger field)."""
+        _check(load().mf_mixing_sweep(ctypes.c_void_p(self.handle), n_sweeps,
+                                      ctypes.c_void_p(self.stream.cuda_stream)))
 
     def sweep_timed(self, n_sweeps: int) -> np.ndarray:
         return mf_gibbs_sweep_timed(self.handle, n_sweeps, self.stream.cuda_stream)

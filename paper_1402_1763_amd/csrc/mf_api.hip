@@ -73,7 +73,7 @@ Shape shape_of(int n) {
 }
 
 struct Layout {
-  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, coef, spec, staging, total;
+  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, coef, spec, staging, total;
   size_t spec_elems, spec_stride;
   int n_wg_x;
 };
@@ -101,7 +101,8 @@ Layout make_layout(const mf_chain_desc& d) {
   L.pk = take(nc * nb * 8);
   L.table = take(nc * nb * 2 * rs);
   L.status = take(nc * 4);
-  L.partials = take(nc * static_cast<size_t>(L.n_wg_x) * nb * 8);
+  L.partials = take(2 * nc * static_cast<size_t>(L.n_wg_x) * nb * 8);   // two sets (mixing)
+  L.ratio = take(nc * nb * 8);
   L.coef = take(nc * 2 * m * rs);
   L.spec = take(nc * L.spec_stride * 2 * rs);
   L.staging = take(m * rs);
@@ -216,6 +217,8 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   a.pk = reinterpret_cast<double*>(ws + p->L.pk);
   a.table = reinterpret_cast<R*>(ws + p->L.table);
   a.partials = reinterpret_cast<double*>(ws + p->L.partials);
+  a.partials2 = a.partials + static_cast<size_t>(p->desc.n_chains) * p->L.n_wg_x * p->desc.n_bins;
+  a.ratio = reinterpret_cast<double*>(ws + p->L.ratio);
   a.qthr = reinterpret_cast<const int32_t*>(ws + p->L.qthr);
   a.counts = reinterpret_cast<const double*>(ws + p->L.counts);
   a.tw = reinterpret_cast<const mf::cx<R>*>(ws + p->L.tw);
@@ -245,7 +248,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
 
 enum KernelId {
   kZ = 0, kYF = 1, kX = 2, kYI = 3, kZSet = 10, kZGet = 11, kTable = 12,
-  kZDetK = 13, kZAccK = 14, kXDetK = 15, kXAdjK = 16
+  kZDetK = 13, kZAccK = 14, kXDetK = 15, kXAdjK = 16, kXMixK = 17, kMixPkK = 18, kXMixInvK = 19
 };
 
 template <typename R, int N>
@@ -295,6 +298,19 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       if constexpr (split)
         hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet>), dim3(N / XS::P, N / 2 + 1, nch),
                            dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+      break;
+    case kXMixK:
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXMix>), dim3(N / XS::P, N / 2 + 1, nch),
+                           dim3(XS::NT), 2 * XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+      break;
+    case kXMixInvK:
+      if constexpr (split)
+        hipLaunchKernelGGL((mf::xmixinv_kernel<R, N>), dim3(N / XS::P, N / 2 + 1, nch), dim3(XS::NT),
+                           a.nb * sizeof(R) + (a.nb + 1) * 4, st, a);
+      break;
+    case kMixPkK:
+      hipLaunchKernelGGL((mf::mix_pk_kernel<R>), dim3(a.nb, nch), dim3(256), 0, st, a);
       break;
     case kXAdjK:
       if constexpr (split)
@@ -578,6 +594,40 @@ mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
   for (int i = 0; i < n_sweeps; ++i) {
     for (int k = 0; k < MF_NUM_KERNELS; ++k) {
       const mf_status st = launch_checked(p, kSweepOrder[k], 0, hs);
+      if (st != MF_OK) return st;
+    }
+    ++p->sweep;
+  }
+  return MF_OK;
+}
+
+mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (n_sweeps < 0) return fail(MF_E_INVALID_ARG, "negative sweep count");
+  if (p->desc.n < 32 || p->desc.n > 256)
+    return fail(MF_E_UNSUPPORTED_SIZE, "the mixing sweep supports grid sides 32 to 256 (got %d)",
+                p->desc.n);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int ids[6] = {kZ, kYF, kXMixK, kMixPkK, kXMixInvK, kYI};
+  for (int i = 0; i < n_sweeps; ++i) {
+    for (int id : ids) {
+      mf_status st;
+      if (id == kYI) {   // P and its table were set by the Metropolis-Hastings move
+        const int nch = p->desc.n_chains;
+        if (p->fp64()) {
+          auto a = args_of<double>(p);
+          a.pk_mode = mf::kPkNone;
+          launch<double>(id, a, p->desc.n, nch, hs);
+        } else {
+          auto a = args_of<float>(p);
+          a.pk_mode = mf::kPkNone;
+          launch<float>(id, a, p->desc.n, nch, hs);
+        }
+        const hipError_t e = hipGetLastError();
+        st = e == hipSuccess ? MF_OK : fail(MF_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
+      } else {
+        st = launch_checked(p, id, 0, hs);
+      }
       if (st != MF_OK) return st;
     }
     ++p->sweep;

@@ -19,7 +19,7 @@
 
 namespace mf {
 
-enum : uint32_t { kPhaseMessenger = 0, kPhaseSignal = 1, kPhaseGamma = 2 };
+enum : uint32_t { kPhaseMessenger = 0, kPhaseSignal = 1, kPhaseGamma = 2, kPhaseMix = 3 };
 constexpr uint32_t kGammaAttempts = 1u << 16;   // counter word 0 = bin * 2^16 + attempt
 
 struct Words4 {

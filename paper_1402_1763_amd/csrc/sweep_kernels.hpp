@@ -39,6 +39,8 @@ struct SweepArgs {
   double* pk;             // [chain][nb]
   R* table;               // [chain][nb][2]
   double* partials;       // [chain][nb][n_wg_x]
+  double* partials2;      // [chain][nb][n_wg_x] second sums (mixing sweep)
+  double* ratio;          // [chain][nb] mixing sweep: sqrt(S^'_b / S^_b)
   const int32_t* qthr;    // [nb] smallest q of every bin
   const double* counts;   // [nb] full-grid modes per bin
   const cx<R>* tw;        // [N] exp(-2 pi i j / N)
@@ -78,7 +80,7 @@ __device__ __forceinline__ int recorded(const SweepArgs<R>& a, uint32_t sweep) {
 }
 
 enum ZMode : int { kZSweep = 0, kZSetState = 1, kZGetState = 2, kZDet = 3, kZAccum = 4 };
-enum XMode : int { kXSample = 0, kXDet = 1, kXAdj = 2 };
+enum XMode : int { kXSample = 0, kXDet = 1, kXAdj = 2, kXMix = 3 };
 enum PkMode : int { kPkDraw = 0, kPkNone = 1, kPkGrad = 2 };
 
 // ---------------------------------------------------------------- tiles
@@ -388,16 +390,16 @@ __device__ __forceinline__ void write_table(R* tab, int b, double p, double tau,
 // conditional of P_b under Jeffreys' prior -- then refreshes (A_b, B_b).
 // With pk_mode == kPkGrad the workgroup instead adds sum_wg partials / M to
 // gacc[b] (the Wiener adjoint's d chi2 / d f_b); kPkNone does nothing.
-template <typename R, int NTH>
-__device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int c, double* red) {
-  if (a.pk_mode == kPkNone) return;
+// Sum of n per-workgroup partials in a fixed order by one workgroup of NTH
+// threads: strided per thread, then a tree in `red` (NTH doubles) folded onto
+// the largest power of two <= NTH.  The result is red[0] (all threads).
+template <int NTH>
+__device__ __forceinline__ double sum_partials(const double* part, int n, double* red) {
   const int tid = threadIdx.x;
-  const double* part = a.partials + (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x;
   double s = 0.0;
-  for (int w = tid; w < a.n_wg_x; w += NTH) s += part[w];
+  for (int w = tid; w < n; w += NTH) s += part[w];
   red[tid] = s;
   __syncthreads();
-  // fixed-order tree: fold onto the largest power of two <= NTH, then halve
   constexpr int P2 = 1 << ilog2(NTH);
   if (P2 < NTH) {
     if (tid < NTH - P2) red[tid] += red[tid + P2];
@@ -407,6 +409,14 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
     if (tid < h) red[tid] += red[tid + h];
     __syncthreads();
   }
+  return red[0];
+}
+
+template <typename R, int NTH>
+__device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int c, double* red) {
+  if (a.pk_mode == kPkNone) return;
+  const int tid = threadIdx.x;
+  sum_partials<NTH>(a.partials + (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x, a.n_wg_x, red);
   if (tid == 0 && a.pk_mode == kPkGrad) {
     a.gacc[static_cast<size_t>(c) * a.nb + b] += red[0] / static_cast<double>(a.m);
   } else if (tid == 0) {
@@ -443,6 +453,92 @@ template <typename R>
 __device__ __forceinline__ void advance_sweep(const SweepArgs<R>& a) {
   if (a.advance && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
     a.ctr[0] = a.ctr[1] + 1u;
+}
+
+// Truncated normal N(mean, sd^2) restricted to (0, inf), drawn exactly with
+// the words of counter (b 2^16 + j, sweep, kPhaseMix, chain), attempt j.
+// a = -mean/sd is the standardised bound; for a <= 0.5 the proposal is the
+// cosine normal of (x0, x1), accepted when z > a; otherwise Robert's
+// exponential proposal z = a - ln(U23(x0)) / r, r = (a + sqrt(a^2 + 4)) / 2,
+// accepted when U23(x1) <= exp(-(z - r)^2 / 2).  u_mh = U23(x3) of attempt 0
+// is the Metropolis-Hastings uniform.  Returns false after kMixAttempts
+// attempts without a proposal.
+constexpr int kMixAttempts = 64;
+
+__device__ inline bool truncated_normal(double mean, double sd, uint32_t b, uint32_t sweep,
+                                        uint32_t chain, uint32_t k0, uint32_t k1, double& u_new,
+                                        double& u_mh) {
+  const double a = -mean / sd;
+  const double r = 0.5 * (a + sqrt(a * a + 4.0));
+  for (int j = 0; j < kMixAttempts; ++j) {
+    const Words4 w = philox4x32_10(b * 65536u + j, sweep, kPhaseMix, chain, k0, k1);
+    if (j == 0) u_mh = u23<double>(w.x3);
+    double z;
+    bool ok;
+    if (a <= 0.5) {
+      double unused;
+      box_muller(w.x0, w.x1, z, unused);
+      ok = z > a;
+    } else {
+      z = a - log(u23<double>(w.x0)) / r;
+      ok = u23<double>(w.x1) <= exp(-0.5 * (z - r) * (z - r));
+    }
+    if (ok) {
+      u_new = mean + sd * z;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Metropolis-Hastings move of S^_b = M P_b in the mixing sweep (Sec. 3.3,
+// shell form), one workgroup per (bin, chain).  With y = s^/M drawn at the
+// current P by the x-pass, H1 = sum w |y|^2 and H2 = sum w Re(conj(y) t^)
+// (partials and partials2) give, for x^ = s^ / sqrt(S^),
+//   X = sum |x^|^2 = M H1 / P,   R = sum Re(conj(x^) t^) = M H2 / sqrt(S^).
+// U = sqrt(S^) has conditional density ~ U^-1 N(U; R/X, T^/X), T^ = M tau;
+// the proposal U' ~ N(R/X, T^/X) truncated to U' > 0 is accepted with
+// probability min(1, U/U').  Writes the new P, its table and the factor
+// ratio = U'/U (1 if rejected) by which the x-pass output is rescaled.
+template <typename R>
+__global__ void __launch_bounds__(256)
+mix_pk_kernel(SweepArgs<R> a) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const size_t off = (static_cast<size_t>(c) * a.nb + b) * a.n_wg_x;
+  const double h1 = sum_partials<256>(a.partials + off, a.n_wg_x, red);
+  __syncthreads();
+  const double h2 = sum_partials<256>(a.partials2 + off, a.n_wg_x, red);
+  if (tid != 0) return;
+  const double m = static_cast<double>(a.m), tau = a.tau[c];
+  const uint32_t sweep = a.ctr[1];
+  double* pk = a.pk + static_cast<size_t>(c) * a.nb;
+  const double p = pk[b];
+  if (a.trace != nullptr) {
+    const int j = recorded(a, sweep);
+    if (j >= 0 && j < a.trace_cap)
+      a.trace[(static_cast<size_t>(c) * a.trace_cap + j) * a.nb + b] = p * a.vcell;
+  }
+  double ratio = 1.0, p_new = p;
+  if (a.counts[b] > 0.0 && h1 > 0.0 && p > 0.0) {
+    const double u = sqrt(m * p);
+    const double xx = m * h1 / p, xt = m * h2 / u;
+    double u_new = 0.0, u_mh = 1.0;
+    if (truncated_normal(xt / xx, sqrt(m * tau / xx), static_cast<uint32_t>(b), sweep,
+                         a.chain0 + c, a.key0, a.key1, u_new, u_mh) &&
+        u_mh <= u / u_new) {
+      p_new = u_new * u_new / m;
+      ratio = u_new / u;
+    }
+    if (!isfinite(p_new) || !(p_new > 0.0) || !isfinite(h1) || !isfinite(h2)) {
+      atomicOr(a.status + c, 1u);
+      p_new = p;
+      ratio = 1.0;
+    }
+  }
+  pk[b] = p_new;
+  a.ratio[static_cast<size_t>(c) * a.nb + b] = ratio;
+  write_table(a.table + static_cast<size_t>(c) * 2 * a.nb, b, p_new, tau, m);
 }
 
 // Table from the current P of every chain (set-up and state restore).
@@ -640,11 +736,18 @@ __device__ __forceinline__ int bin_of(int q, const int32_t* qthr, int nb, float 
   return b + (q >= hi ? 1 : 0) - (q < lo ? 1 : 0);
 }
 
+// Re(conj(u) t) in FP64 (products of FP32 values are exact there).
+template <typename R>
+__device__ __forceinline__ double cross(cx<R> u, cx<R> t) {
+  return static_cast<double>(u.x) * t.x + static_cast<double>(u.y) * t.y;
+}
+
 template <typename R>
 struct DrawCtx {
   const int32_t* qthr;    // LDS
   const cx<R>* tab;       // LDS, (A_b, B_b)
   double* hist;           // this lane's LDS histogram
+  double* hist2;          // its second histogram (mixing sweep) or nullptr
   float qscale;
   int nb;
   uint32_t chain;
@@ -663,7 +766,7 @@ struct DrawCtx {
 // w of the plane (1 on kz = 0, N/2, else 2) is applied per workgroup in
 // draw_epilogue.  This is the form for planes 0 < kz < N/2, where every
 // mode is drawn independently and q >= 1.
-template <typename R, int N, int RL, int S>
+template <typename R, int N, int RL, int S, bool MIX>
 __device__ __forceinline__ void draw_slot_plain(cx<R>* v, int q, int iy, int kz,
                                                 const SweepArgs<R>& a, const DrawCtx<R>& d) {
   constexpr int H = N / 2;
@@ -688,6 +791,7 @@ __device__ __forceinline__ void draw_slot_plain(cx<R>* v, int q, int iy, int kz,
       const cx<R> t = v[e];
       const cx<R> out{ab.x * t.x + ab.y * g[2 * h], ab.x * t.y + ab.y * g[2 * h + 1]};
       atomicAdd(d.hist + b, static_cast<double>(out.x * out.x + out.y * out.y));
+      if (MIX) atomicAdd(d.hist2 + b, cross(out, t));
       v[e] = out;
     }
   }
@@ -697,7 +801,7 @@ __device__ __forceinline__ void draw_slot_plain(cx<R>* v, int q, int iy, int kz,
 // the plane: self-conjugate modes are real with the full variance; the member
 // of a conjugate pair with the larger ix*N + iy uses its partner's normals
 // conjugated; q = 0 gives 0.
-template <typename R, int N, int RL, int S>
+template <typename R, int N, int RL, int S, bool MIX>
 __device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
                                                const SweepArgs<R>& a, const DrawCtx<R>& d) {
   constexpr int H = N / 2;
@@ -732,6 +836,7 @@ __device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
         else
           out = cx<R>{ab.x * t.x + ab.y * g[2 * h], ab.x * t.y + ab.y * g[2 * h + 1]};
         atomicAdd(d.hist + b, static_cast<double>(out.x * out.x + out.y * out.y));
+        if (MIX) atomicAdd(d.hist2 + b, cross(out, t));
       }
       v[e] = out;
     }
@@ -752,15 +857,18 @@ __device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
     const cx<R> t = v[e];
     const cx<R> out{ab.x * t.x + ab.y * g0, ab.x * t.y - ab.y * g1};
     atomicAdd(d.hist + b, static_cast<double>(out.x * out.x + out.y * out.y));
+    if (MIX) atomicAdd(d.hist2 + b, cross(out, t));
     v[e] = out;
   }
 }
 
-template <typename R, int N, int RL, int S>
+// MIX = true also adds Re(conj(s^/M) t^) to the second histogram (the
+// mixing sweep's cross term).
+template <typename R, int N, int RL, int S, bool MIX = false>
 __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
                                           const SweepArgs<R>& a, const DrawCtx<R>& d) {
-  if (kz == 0 || kz == N / 2) draw_slot_herm<R, N, RL, S>(v, q, iy, kz, a, d);
-  else draw_slot_plain<R, N, RL, S>(v, q, iy, kz, a, d);
+  if (kz == 0 || kz == N / 2) draw_slot_herm<R, N, RL, S, MIX>(v, q, iy, kz, a, d);
+  else draw_slot_plain<R, N, RL, S, MIX>(v, q, iy, kz, a, d);
 }
 
 // Deterministic counterpart of draw_slot for the Wiener iteration: every mode
@@ -796,20 +904,22 @@ __device__ __forceinline__ void filter_slot(cx<R>* v, int q, int iy, int kz, con
 
 // Shared prologue / epilogue of the x-pass kernels: LDS tables and per-wave
 // histograms (HG copies per wave by lane), then one partial per workgroup.
-template <typename R, int NT, int NHIST, int HG>
+// NH histogram sets (1, or 2 for the mixing sweep) of NHIST copies each.
+template <typename R, int NT, int NHIST, int HG, int NH = 1>
 __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c, double* dyn,
                                                     int n) {
   const int nb = a.nb, tid = threadIdx.x;
   double* hist = dyn;
-  R* tab = reinterpret_cast<R*>(hist + NHIST * nb);
+  R* tab = reinterpret_cast<R*>(hist + NH * NHIST * nb);
   int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * nb);
-  for (int i = tid; i < NHIST * nb; i += NT) hist[i] = 0.0;
+  for (int i = tid; i < NH * NHIST * nb; i += NT) hist[i] = 0.0;
   for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
   for (int i = tid; i <= nb; i += NT) qthr[i] = i < nb ? a.qthr[i] : INT32_MAX;
   DrawCtx<R> d;
   d.qthr = qthr;
   d.tab = reinterpret_cast<const cx<R>*>(tab);
   d.hist = hist + ((tid / 64) * HG + (tid % HG)) * nb;
+  d.hist2 = NH == 2 ? d.hist + NHIST * nb : nullptr;
   d.qscale = static_cast<float>(4.0 * nb * nb / (3.0 * n * n));
   d.nb = nb;
   d.chain = a.chain0 + c;
@@ -822,10 +932,10 @@ __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c
 // and its conjugate).
 template <typename R, int NT, int NHIST>
 __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, double* hist, int wg,
-                                              double wgt) {
+                                              double wgt, double* partials = nullptr) {
   __syncthreads();   // all histogram atomics are done
   const int nb = a.nb, tid = threadIdx.x;
-  double* part = a.partials + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
+  double* part = (partials ? partials : a.partials) + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
   // Fixed-order reduction of the NHIST copies: G groups of PER consecutive
   // copies, each summed in ascending order into its first copy (every entry is
   // read and written by one thread only), then the G group sums in order.
@@ -873,7 +983,8 @@ xsplit_kernel(SweepArgs<R> a) {
   const int iy0 = blockIdx.x * P;
   const int kz = blockIdx.y;
   const int c = blockIdx.z;
-  const DrawCtx<R> d = draw_prologue<R, NT, T::NHIST, T::HG>(a, c, dyn, N);
+  constexpr int NH = XM == kXMix ? 2 : 1;
+  const DrawCtx<R> d = draw_prologue<R, NT, T::NHIST, T::HG, NH>(a, c, dyn, N);
   const int col = tid % P, k1 = tid / P;
   cx<R>* base = a.spec + static_cast<size_t>(c) * a.spec_stride +
                 (static_cast<size_t>(kz) * N + 16 * k1) * N + iy0 + col;
@@ -882,18 +993,61 @@ xsplit_kernel(SweepArgs<R> a) {
   for (int j = 0; j < 16; ++j) v[j] = base[static_cast<size_t>(j) * N];
   dft<R, 16, false>(v);                 // v[k2] = X[k1 + NA k2]
   __syncthreads();                      // tables and histograms ready
-  if (XM == kXSample) {
-    draw_slot<R, N, 16, NA>(v, k1, iy0 + col, kz, a, d);
+  if (XM == kXSample || XM == kXMix) {
+    draw_slot<R, N, 16, NA, XM == kXMix>(v, k1, iy0 + col, kz, a, d);
   } else {
     cx<R>* aux = a.aux == nullptr ? nullptr : a.aux + (base - a.spec);
     filter_slot<R, N, 16, NA, XM>(v, k1, iy0 + col, kz, d, aux, N);
   }
+  // the mixing sweep stores the drawn modes untransformed (row 16 k1 + j
+  // holds mode k1 + NA j) for the rescaling pass, which runs the inverse
+  if (XM != kXMix) dft<R, 16, true>(v);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) base[static_cast<size_t>(j) * N] = v[j];
+  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+  if (XM != kXDet) draw_epilogue<R, NT, T::NHIST>(a, c, dyn, wg, wgt);
+  if (XM == kXMix) draw_epilogue<R, NT, T::NHIST>(a, c, dyn + T::NHIST * a.nb, wg, wgt, a.partials2);
+}
+
+// Second half of the mixing sweep's x-pass: every mode of bin b, stored by
+// xsplit_kernel<.., kXMix> in its post-DFT layout, is multiplied by ratio_b =
+// sqrt(S^'_b / S^_b) from the Metropolis-Hastings move, then the inverse
+// 16-point DFT restores the split layout for the inverse y-pass.
+template <typename R, int N>
+__global__ void __launch_bounds__((XSTile<R, N>::NT))
+xmixinv_kernel(SweepArgs<R> a) {
+  using T = XSTile<R, N>;
+  constexpr int P = T::P, NT = T::NT, NA = T::NA;
+  extern __shared__ double dyn[];      // ratio (nb R), qthr (nb + 1)
+  const int tid = threadIdx.x, nb = a.nb;
+  const int iy0 = blockIdx.x * P, kz = blockIdx.y, c = blockIdx.z;
+  R* rat = reinterpret_cast<R*>(dyn);
+  int32_t* qthr = reinterpret_cast<int32_t*>(rat + nb);
+  for (int i = tid; i < nb; i += NT) rat[i] = static_cast<R>(a.ratio[static_cast<size_t>(c) * nb + i]);
+  for (int i = tid; i <= nb; i += NT) qthr[i] = i < nb ? a.qthr[i] : INT32_MAX;
+  const float qscale = static_cast<float>(4.0 * nb * nb / (3.0 * N * N));
+  const int col = tid % P, k1 = tid / P;
+  cx<R>* base = a.spec + static_cast<size_t>(c) * a.spec_stride +
+                (static_cast<size_t>(kz) * N + 16 * k1) * N + iy0 + col;
+  cx<R> v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = base[static_cast<size_t>(j) * N];
+  __syncthreads();
+  const int my = wavenumber(iy0 + col, N);
+  const int r2 = my * my + kz * kz;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int mx = wavenumber(k1 + NA * j, N);
+    const int q = mx * mx + r2;
+    if (q > 0) {
+      const R f = rat[bin_of(q, qthr, nb, qscale)];
+      v[j] = cx<R>{v[j].x * f, v[j].y * f};
+    }
+  }
   dft<R, 16, true>(v);
 #pragma unroll
   for (int j = 0; j < 16; ++j) base[static_cast<size_t>(j) * N] = v[j];
-  if (XM != kXDet)
-    draw_epilogue<R, NT, T::NHIST>(a, c, dyn, blockIdx.y * gridDim.x + blockIdx.x,
-                                   (kz == 0 || kz == N / 2) ? 1.0 : 2.0);
 }
 
 // Whole-transform x-pass (N = 8, 16, 512): workgroup = one kz plane and P
