@@ -47,21 +47,6 @@ def x_columns(n: int) -> int:
     return min(n, 4096 // n)
 
 
-def algorithmic_bytes(n: int, real_bytes: int, n_bins: int, n_wg_x: int) -> dict:
-    """Bytes each sweep kernel must move: the half-complex field is read and
-    written once per pass, the z-pass also reads the two messenger
-    coefficients per voxel; the P draw (inside the inverse y-pass) reads the
-    shell partials."""
-    m = n ** 3
-    spec = (n // 2 + 1) * n * n * 2 * real_bytes
-    return {
-        "zpass": 2 * spec + 2 * m * real_bytes,
-        "yfwd": 2 * spec,
-        "xpass": 2 * spec + n_wg_x * n_bins * 8,
-        "yinv_pk": 2 * spec + n_wg_x * n_bins * 8 + n_bins * (16 + 2 * real_bytes),
-    }
-
-
 def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch measured by rocprofv3 counters, if recorded for
     the current kernel sources."""
@@ -115,8 +100,7 @@ def bench_batched(args):
                                         [pb["pk_init"] for pb in pbs], 16, ws[0].box,
                                         seed=ws[0].rng_seed, precision="fp32"))
         chain_voxels += chains * n ** 3
-        n_wg_x = (n // 2 + 1) * (n // x_columns(n))
-        sweep_bytes += chains * sum(algorithmic_bytes(n, 4, 16, n_wg_x).values())
+        sweep_bytes += sum(samplers[-1].sweep_bytes().values())
     graph = binding.SweepGraph(samplers)
     stream = torch.cuda.current_stream()
     graph.launch(args.warmup)
@@ -183,7 +167,7 @@ def bench_mixing(args):
     n = w.n
     n_wg_x = (n // 2 + 1) * (n // x_columns(n))
     spec = 8 * (n // 2 + 1) * n * n
-    nbytes = (sum(algorithmic_bytes(n, 4, w.n_bins, n_wg_x).values())
+    nbytes = (sum(smp.sweep_bytes().values())
               + 2 * spec + 2 * n_wg_x * w.n_bins * 8)        # rescaling pass, cross sums
     out = {
         "metric": "mixing sweeps/s at 256^3 FP32 (Alg. 3, shell form)",
@@ -197,19 +181,23 @@ def bench_mixing(args):
     print(json.dumps(out), flush=True)
 
 
-def wiener_grad_bytes(n: int, real_bytes: int, n_bins: int, n_iter: int, every: int) -> int:
+def wiener_grad_bytes(n: int, real_bytes: int, n_bins: int, n_iter: int, every: int,
+                      coef_frac: float = 1.0) -> int:
     """Algorithmic HBM bytes of one chi2 forward + backward run of the
     messenger Wiener filter (K iterations, checkpoint every E): K plain
     iterations, K recomputed ones that store t^, K adjoint iterations that
-    read it back and accumulate the adjoint field, plus set-up and read-out."""
+    read it back and accumulate the adjoint field, plus set-up and read-out.
+    coef_frac: share of the coefficients the z-pass reads (tiles with an
+    observed voxel)."""
     m = n ** 3
     spec = 2 * real_bytes * (n // 2 + 1) * n * n  # half-complex field
     coef = 2 * real_bytes * m                      # (alpha, beta) per voxel
+    zcoef = int(coef * coef_frac)
     field = real_bytes * m                         # one real field
     n_wg_x = (n // 2 + 1) * (n // x_columns(n))
     partials = 2 * n_wg_x * n_bins * 8
     n_ckpt = -(-n_iter // every)
-    plain = 8 * spec + coef                        # z, y, x, y passes
+    plain = 8 * spec + zcoef                       # z, y, x, y passes
     store = plain + spec                           # + t^ written
     adjoint = plain + spec + 2 * field + partials  # + t^ read, adjoint field summed
     forward_extra = (coef + 8 * m + coef           # data -> (alpha, beta)
@@ -260,7 +248,9 @@ def bench_wiener(args):
     torch.cuda.synchronize()
     fwd_ms, bwd_ms = start.elapsed_time(mid), mid.elapsed_time(stop)
     assert np.isfinite(float(chi2)) and bool(torch.isfinite(gp).all())
-    nbytes = wiener_grad_bytes(w.n, 4, w.n_bins, n_iter, every)
+    spec = 8 * (w.n // 2 + 1) * w.n ** 2
+    coef_frac = (smp.sweep_bytes()["zpass"] - 2 * spec) / (8 * w.m)
+    nbytes = wiener_grad_bytes(w.n, 4, w.n_bins, n_iter, every, coef_frac)
     out = {
         "metric": "messenger Wiener-filter chi2 + gradient evaluations/s (128^3, 50 iterations, "
                   "checkpoint every 10)",
@@ -367,8 +357,7 @@ def main():
 
     real_bytes = 8 if w.precision == "fp64" else 4
     n = w.n
-    n_wg_x = (n // 2 + 1) * (n // x_columns(n))
-    alg = algorithmic_bytes(n, real_bytes, w.n_bins, n_wg_x)
+    alg = smp.sweep_bytes()
     sweep_bytes = sum(alg.values())
 
     roofline = None
@@ -383,6 +372,7 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "kernel": dom,
                     "algorithmic_bytes_per_launch": alg[dom],
+                    "algorithmic_bytes": alg,
                     "kernel_ms": {k: round(v, 5) for k, v in kernel_ms.items()}}
     smp.close()
 

@@ -164,6 +164,17 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
  * Errors: MF_E_UNSUPPORTED_SIZE, MF_E_INVALID_ARG, MF_E_DEVICE. */
 mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
 
+/* Algorithmic HBM bytes of one sweep, per kernel (bytes[MF_NUM_KERNELS], in
+ * sweep order), summed over the problem's chains.  Each pass reads and
+ * writes the half-complex field once, 2 (N/2 + 1) N^2 reals each way.  On
+ * top of that:
+ *  - the z-pass reads the two messenger coefficients of every voxel in its
+ *    tiles that hold an observed voxel (tiles with none skip the read);
+ *  - the x-pass writes one FP64 shell partial per bin and workgroup;
+ *  - the inverse y-pass reads those partials and updates P and its table.
+ * These are the per-unit figures behind the roofline of each kernel. */
+mf_status mf_sweep_bytes(const mf_problem* p, size_t* bytes);
+
 /* The messenger variance tau of a chain (host value). */
 mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out);
 

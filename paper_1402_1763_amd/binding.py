@@ -67,6 +67,7 @@ SIGNATURES = {
     "mf_set_chain_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
                                           _c_double_p, ctypes.c_uint64, ctypes.c_void_p]),
     "mf_get_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p]),
+    "mf_sweep_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "mf_debug_run_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
                                            ctypes.c_void_p]),
     "mf_debug_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
@@ -367,6 +368,12 @@ class Sampler:
 
     def set_state(self, chain: int, s, pk, sweep: int):
         mf_set_chain_state(self.handle, chain, s, pk, sweep, self.stream.cuda_stream)
+
+    def sweep_bytes(self) -> dict:
+        """Algorithmic HBM bytes of one sweep per kernel (all chains)."""
+        out = (ctypes.c_size_t * MF_NUM_KERNELS)()
+        _check(load().mf_sweep_bytes(ctypes.c_void_p(self.handle), out))
+        return dict(zip(KERNEL_NAMES, (int(v) for v in out)))
 
     def tau(self, chain: int = 0) -> float:
         return mf_get_tau(self.handle, chain)

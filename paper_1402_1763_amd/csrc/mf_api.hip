@@ -54,26 +54,29 @@ struct Geometry {
     else return mf::XTile<R, N>::P;
   }
   static constexpr int xp = columns();
+  static constexpr int ztiles = (N / mf::ZTile<R, N>::IXB) * (N / mf::ZTile<R, N>::P);
 };
 
 struct Shape {
-  int xp;   // columns per x-pass workgroup
+  int xp;       // columns per x-pass workgroup
+  int ztiles;   // z-pass tiles per chain
 };
 
 template <typename R>
 Shape shape_of(int n) {
   switch (n) {
 #define MF_SHAPE(NN) \
-  case NN: return Shape{Geometry<R, NN>::xp};
+  case NN: return Shape{Geometry<R, NN>::xp, Geometry<R, NN>::ztiles};
     MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(48) MF_SHAPE(64) MF_SHAPE(80) MF_SHAPE(96)
     MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
 #undef MF_SHAPE
   }
-  return Shape{0};
+  return Shape{0, 0};
 }
 
 struct Layout {
-  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, coef, spec, staging, total;
+  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, tobs, coef, spec, staging,
+      total;
   size_t spec_elems, spec_stride;
   int n_wg_x;
 };
@@ -103,6 +106,7 @@ Layout make_layout(const mf_chain_desc& d) {
   L.status = take(nc * 4);
   L.partials = take(2 * nc * static_cast<size_t>(L.n_wg_x) * nb * 8);   // two sets (mixing)
   L.ratio = take(nc * nb * 8);
+  L.tobs = take(nc * static_cast<size_t>(sh.ztiles));
   L.coef = take(nc * 2 * m * rs);
   L.spec = take(nc * L.spec_stride * 2 * rs);
   L.staging = take(m * rs);
@@ -201,6 +205,7 @@ struct mf_problem {
   uint64_t sweep;
   WienerRun wiener;
   DiagRec diag;
+  std::vector<int> obs_tiles;   // per chain: z-pass tiles holding an observed voxel
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
 
@@ -212,6 +217,8 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   char* ws = p->ws;
   a.spec = reinterpret_cast<mf::cx<R>*>(ws + p->L.spec);
   a.coef = reinterpret_cast<const R*>(ws + p->L.coef);
+  a.tile_obs = reinterpret_cast<const uint8_t*>(ws + p->L.tobs);
+  a.ztiles = p->sh.ztiles;
   a.staging = reinterpret_cast<R*>(ws + p->L.staging);
   a.tau = reinterpret_cast<const double*>(ws + p->L.tau);
   a.pk = reinterpret_cast<double*>(ws + p->L.pk);
@@ -402,10 +409,12 @@ mf_status download_real(mf_problem* p, double* dst, const void* src, size_t coun
 }
 
 template <typename R, int N>
-void permute_coef(std::vector<R>& out, const double* data, const double* noise_var, double tau) {
+void permute_coef(std::vector<R>& out, std::vector<uint8_t>& obs, const double* data,
+                  const double* noise_var, double tau) {
   using T = mf::ZTile<R, N>;
   const int tiles = (N / T::IXB) * (N / T::P);
   out.assign(static_cast<size_t>(2) * N * N * N, R(0));
+  obs.assign(tiles, 0);
   auto alpha = [&](size_t i) { return std::isinf(noise_var[i]) ? 1.0 : 1.0 - tau / noise_var[i]; };
   auto beta = [&](size_t i) { return std::isinf(noise_var[i]) ? 0.0 : tau * data[i] / noise_var[i]; };
   for (int tile = 0; tile < tiles; ++tile)
@@ -419,6 +428,7 @@ void permute_coef(std::vector<R>& out, const double* data, const double* noise_v
         o[1] = static_cast<R>(alpha(vb));
         o[2] = static_cast<R>(beta(va));
         o[3] = static_cast<R>(beta(vb));
+        if (!std::isinf(noise_var[va]) || !std::isinf(noise_var[vb])) obs[tile] = 1;
       }
 }
 
@@ -426,20 +436,20 @@ template <typename R>
 mf_status upload_coef(mf_problem* p, int c, const double* data, const double* noise_var,
                       double tau, hipStream_t st) {
   std::vector<R> buf;
+  std::vector<uint8_t> obs;
   switch (p->desc.n) {
-    case 8: permute_coef<R, 8>(buf, data, noise_var, tau); break;
-    case 16: permute_coef<R, 16>(buf, data, noise_var, tau); break;
-    case 32: permute_coef<R, 32>(buf, data, noise_var, tau); break;
-    case 48: permute_coef<R, 48>(buf, data, noise_var, tau); break;
-    case 64: permute_coef<R, 64>(buf, data, noise_var, tau); break;
-    case 80: permute_coef<R, 80>(buf, data, noise_var, tau); break;
-    case 96: permute_coef<R, 96>(buf, data, noise_var, tau); break;
-    case 128: permute_coef<R, 128>(buf, data, noise_var, tau); break;
-    case 256: permute_coef<R, 256>(buf, data, noise_var, tau); break;
-    case 512: permute_coef<R, 512>(buf, data, noise_var, tau); break;
+#define MF_PERMUTE(NN) \
+  case NN: permute_coef<R, NN>(buf, obs, data, noise_var, tau); break;
+    MF_PERMUTE(8) MF_PERMUTE(16) MF_PERMUTE(32) MF_PERMUTE(48) MF_PERMUTE(64) MF_PERMUTE(80)
+    MF_PERMUTE(96) MF_PERMUTE(128) MF_PERMUTE(256) MF_PERMUTE(512)
+#undef MF_PERMUTE
   }
   MF_HIP(hipMemcpyAsync(p->ws + p->L.coef + static_cast<size_t>(c) * buf.size() * sizeof(R),
                         buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st));
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.tobs + static_cast<size_t>(c) * obs.size(), obs.data(),
+                        obs.size(), hipMemcpyHostToDevice, st));
+  if (p->obs_tiles.size() < static_cast<size_t>(p->desc.n_chains)) p->obs_tiles.resize(p->desc.n_chains);
+  p->obs_tiles[c] = static_cast<int>(std::count(obs.begin(), obs.end(), uint8_t{1}));
   MF_HIP(hipStreamSynchronize(st));
   return MF_OK;
 }
@@ -774,6 +784,21 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
   if (st != MF_OK) return st;
   p->sweep = h.sweep;
   return write_counter(p, h.sweep, hs);
+}
+
+mf_status mf_sweep_bytes(const mf_problem* p, size_t* bytes) {
+  if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
+  const size_t rs = p->fp64() ? 8 : 4, n = p->desc.n, m = n * n * n, nb = p->desc.n_bins;
+  const size_t spec = (n / 2 + 1) * n * n * 2 * rs, part = static_cast<size_t>(p->L.n_wg_x) * nb * 8;
+  for (int k = 0; k < MF_NUM_KERNELS; ++k) bytes[k] = 0;
+  for (int c = 0; c < p->desc.n_chains; ++c) {
+    const size_t coef = 2 * m * rs * static_cast<size_t>(p->obs_tiles[c]) / p->sh.ztiles;
+    bytes[0] += 2 * spec + coef;
+    bytes[1] += 2 * spec;
+    bytes[2] += 2 * spec + part;
+    bytes[3] += 2 * spec + part + nb * (16 + 2 * rs);
+  }
+  return MF_OK;
 }
 
 mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out) {

@@ -34,6 +34,8 @@ template <typename R>
 struct SweepArgs {
   cx<R>* spec;            // chain c at spec + c * spec_stride
   const R* coef;          // chain c at coef + c * 2 m (z-pass thread order)
+  const uint8_t* tile_obs;  // [chain][z tile] 0 when every voxel of the tile is unobserved
+  int32_t ztiles;         // z-pass tiles per chain
   R* staging;             // M reals, shared by all chains (state in/out)
   const double* tau;      // [chain]
   double* pk;             // [chain][nb]
@@ -193,6 +195,16 @@ __host__ __device__ inline void zpass_coef_voxel(int tile, int e, int tid, int& 
   iya = (tile % (N / T::P)) * T::P + 2 * (pen % T::NPAIR);
 }
 
+// Whether z-pass tile `tile` of chain c holds an observed voxel.  Tiles with
+// none skip their coefficient loads: alpha = 1 and beta = 0 there exactly.
+// The flag is the same for the whole workgroup.
+template <typename R>
+__device__ __forceinline__ bool tile_observed(const SweepArgs<R>& a, int c, int tile) {
+  if (a.tile_obs == nullptr) return true;
+  const int f = a.tile_obs[static_cast<size_t>(c) * a.ztiles + tile];
+  return __builtin_amdgcn_readfirstlane(f) != 0;
+}
+
 // Workgroup = IXB consecutive ix and P consecutive iy; z pencils (iy, iy + 1)
 // are packed as one complex pencil a + i b.
 //   load    : Z_k = A_k + i B_k from the half spectra, Hermitian-extended
@@ -307,19 +319,21 @@ zpass_kernel(SweepArgs<R> a) {
       v[e] = cx<R>{a.staging[ra] * inv_n, a.staging[ra + N] * inv_n};
     }
   } else if (MODE == kZDet) {
-    const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m +
-                    static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 4;
+    const int tile = blockIdx.y * (N / T::P) + blk;
+    const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m + static_cast<size_t>(tile) * EPT * NT * 4;
+    const bool obs = tile_observed(a, c, tile);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      R cf[4];
-      ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
+      R cf[4] = {R(1), R(1), R(0), R(0)};
+      if (obs) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
       const cx<R> s = v[e];
       v[e] = cx<R>{a.cs * cf[0] * s.x + a.cb * cf[2], a.cs * cf[1] * s.y + a.cb * cf[3]};
     }
   } else {
     const R tau = static_cast<R>(a.tau[c]);
-    const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m +
-                    static_cast<size_t>(blockIdx.y * (N / T::P) + blk) * EPT * NT * 4;
+    const int tile = blockIdx.y * (N / T::P) + blk;
+    const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m + static_cast<size_t>(tile) * EPT * NT * 4;
+    const bool obs = tile_observed(a, c, tile);
     const uint32_t chain = a.chain0 + c;
 #pragma unroll
     for (int i = 0; i < EPT / RL; ++i) {
@@ -345,8 +359,8 @@ zpass_kernel(SweepArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int e = i * RL + cq + j * (RL / 4);
-          R cf[4];
-          ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
+          R cf[4] = {R(1), R(1), R(0), R(0)};
+          if (obs) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
           const cx<R> s = v[e];
           const R ta = cf[0] * s.x + cf[2] + sqrt(tau * cf[0]) * ga[j];
           const R tb = cf[1] * s.y + cf[3] + sqrt(tau * cf[1]) * gb[j];
