@@ -101,6 +101,9 @@ def bench_batched(args):
                                         seed=ws[0].rng_seed, precision="fp32"))
         chain_voxels += chains * n ** 3
         sweep_bytes += sum(samplers[-1].sweep_bytes().values())
+    tuned = {}
+    for (n, _), smp in zip(workloads.BATCHED_SIZES, samplers):
+        tuned[f"{n}^3"] = smp.autotune(trials=10)["path"]   # before the graph is captured
     graph = binding.SweepGraph(samplers)
     stream = torch.cuda.current_stream()
     graph.launch(args.warmup)
@@ -133,6 +136,7 @@ def bench_batched(args):
         "data": "synthetic",
         "config": {"workload": "gibbs-batched-mixed",
                    "chains": {f"{n}^3": c for n, c in workloads.BATCHED_SIZES},
+                   "x_path": tuned,
                    "chain_sweeps_per_s": round(chains * 1000.0 / ms, 1),
                    "voxel_sweeps_per_s": round(chain_voxels * 1000.0 / ms, 1),
                    "sweep_bytes_algorithmic": sweep_bytes,
@@ -337,6 +341,7 @@ def main():
     smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
                           seed=w.rng_seed, precision=w.precision)
     stream = torch.cuda.current_stream()
+    tune = smp.autotune(trials=20)      # set-up: picks the x-transform path, chain unchanged
     smp.sweep(args.warmup)
     torch.cuda.synchronize()
 
@@ -393,6 +398,8 @@ def main():
                    "precision": "FP32 fields/FFTs/draws, FP64 shell sums and P draws",
                    "mask": "sphere r<0.45L minus seeded 30deg wedge",
                    "chains": 1,
+                   "x_path": tune["path"],
+                   "autotune_ms_per_sweep": {k: round(v, 5) for k, v in tune["ms"].items()},
                    "sweep_bytes_algorithmic": sweep_bytes,
                    "sweep_hbm_frac": round(sweep_bytes / (ms_per_step * 1e-3) / 1e9
                                            / HBM_PEAK_GBS, 4),

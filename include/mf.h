@@ -164,6 +164,26 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
  * Errors: MF_E_UNSUPPORTED_SIZE, MF_E_INVALID_ARG, MF_E_DEVICE. */
 mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
 
+/* How Gibbs sweeps run the x transform, and its autotuner.
+ * Path 0 (split, 32 <= N <= 256): the y-passes also run the radix-N/16 half
+ * of the x-DFT, and the x-pass runs 16-point DFTs in registers.
+ * Path 1 (whole): the x-pass runs whole x pencils through LDS.  It is the
+ * only path for N = 8, 16, 512.
+ * Both paths give the same chain up to rounding and leave the same state
+ * between sweeps, so they may be switched at any time.  The default is the
+ * split path where it exists.  Mixing sweeps and the Wiener filter always
+ * use the split path.
+ * mf_set_x_path: MF_E_UNSUPPORTED_SIZE for the split path outside 32..256.
+ * mf_autotune: times `trials` Gibbs sweeps of the problem on each available
+ * path (after one warm-up sweep each) and selects the faster.  ms[path]
+ * receives the mean sweep time in ms, NaN for a path not available.  Every
+ * chain's state (spectrum, P, sweep index) is saved to host memory first and
+ * restored bitwise afterwards.  Diagnostic recording is suspended meanwhile.
+ * Synchronises `stream`. */
+mf_status mf_set_x_path(mf_problem* p, int32_t path);
+mf_status mf_get_x_path(const mf_problem* p, int32_t* path);
+mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, int32_t* path_out);
+
 /* Algorithmic HBM bytes of one sweep, per kernel (bytes[MF_NUM_KERNELS], in
  * sweep order), summed over the problem's chains.  Each pass reads and
  * writes the half-complex field once, 2 (N/2 + 1) N^2 reals each way.  On

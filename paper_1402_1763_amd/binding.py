@@ -68,6 +68,10 @@ SIGNATURES = {
                                           _c_double_p, ctypes.c_uint64, ctypes.c_void_p]),
     "mf_get_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p]),
     "mf_sweep_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_set_x_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "mf_get_x_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "mf_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, _c_double_p,
+                                   ctypes.POINTER(ctypes.c_int32)]),
     "mf_debug_run_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
                                            ctypes.c_void_p]),
     "mf_debug_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
@@ -368,6 +372,25 @@ class Sampler:
 
     def set_state(self, chain: int, s, pk, sweep: int):
         mf_set_chain_state(self.handle, chain, s, pk, sweep, self.stream.cuda_stream)
+
+    X_PATHS = ("split", "whole")
+
+    def set_x_path(self, path: str):
+        _check(load().mf_set_x_path(ctypes.c_void_p(self.handle), self.X_PATHS.index(path)))
+
+    def x_path(self) -> str:
+        out = ctypes.c_int32(0)
+        _check(load().mf_get_x_path(ctypes.c_void_p(self.handle), ctypes.byref(out)))
+        return self.X_PATHS[out.value]
+
+    def autotune(self, trials: int = 20) -> dict:
+        """Time both x-transform paths and keep the faster; returns
+        {"path": ..., "ms": {"split": ..., "whole": ...}} (state unchanged)."""
+        ms = (ctypes.c_double * 2)()
+        path = ctypes.c_int32(0)
+        _check(load().mf_autotune(ctypes.c_void_p(self.handle), trials,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ms, ctypes.byref(path)))
+        return {"path": self.X_PATHS[path.value], "ms": dict(zip(self.X_PATHS, list(ms)))}
 
     def sweep_bytes(self) -> dict:
         """Algorithmic HBM bytes of one sweep per kernel (all chains)."""

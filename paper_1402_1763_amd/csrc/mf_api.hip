@@ -47,38 +47,46 @@ bool supported(int n) {
          n == 256 || n == 512;
 }
 
+// The two ways of running the x transform.  kPathSplit (32 <= N <= 256):
+// the y-passes carry its radix-N/16 half, and the x-pass runs 16-point DFTs
+// in registers.  kPathWhole: the x-pass runs whole x pencils through LDS.
+// Both leave the same state between sweeps, so a problem may switch.
+enum XPath : int { kPathSplit = 0, kPathWhole = 1 };
+
 template <typename R, int N>
 struct Geometry {
-  static constexpr int columns() {
+  static constexpr int split_columns() {
     if constexpr (mf::split_x<N>()) return mf::XSTile<R, N>::P;
     else return mf::XTile<R, N>::P;
   }
-  static constexpr int xp = columns();
+  static constexpr int xp_split = split_columns();
+  static constexpr int xp_whole = mf::XTile<R, N>::P;
   static constexpr int ztiles = (N / mf::ZTile<R, N>::IXB) * (N / mf::ZTile<R, N>::P);
 };
 
 struct Shape {
-  int xp;       // columns per x-pass workgroup
-  int ztiles;   // z-pass tiles per chain
+  int xp_split, xp_whole;   // columns per x-pass workgroup on each path
+  int ztiles;               // z-pass tiles per chain
 };
 
 template <typename R>
 Shape shape_of(int n) {
   switch (n) {
 #define MF_SHAPE(NN) \
-  case NN: return Shape{Geometry<R, NN>::xp, Geometry<R, NN>::ztiles};
+  case NN: return Shape{Geometry<R, NN>::xp_split, Geometry<R, NN>::xp_whole, Geometry<R, NN>::ztiles};
     MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(48) MF_SHAPE(64) MF_SHAPE(80) MF_SHAPE(96)
     MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
 #undef MF_SHAPE
   }
-  return Shape{0, 0};
+  return Shape{0, 0, 0};
 }
 
 struct Layout {
   size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, tobs, coef, spec, staging,
       total;
   size_t spec_elems, spec_stride;
-  int n_wg_x;
+  int n_wg_split, n_wg_whole;   // x-pass workgroups (one shell partial each) per path
+  int n_wg_max;
 };
 
 Layout make_layout(const mf_chain_desc& d) {
@@ -89,7 +97,9 @@ Layout make_layout(const mf_chain_desc& d) {
   Layout L{};
   L.spec_elems = (n / 2 + 1) * n * n;
   L.spec_stride = align_up(L.spec_elems * 2 * rs) / (2 * rs);
-  L.n_wg_x = static_cast<int>((n / 2 + 1) * (n / sh.xp));
+  L.n_wg_split = static_cast<int>((n / 2 + 1) * (n / sh.xp_split));
+  L.n_wg_whole = static_cast<int>((n / 2 + 1) * (n / sh.xp_whole));
+  L.n_wg_max = std::max(L.n_wg_split, L.n_wg_whole);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -104,7 +114,7 @@ Layout make_layout(const mf_chain_desc& d) {
   L.pk = take(nc * nb * 8);
   L.table = take(nc * nb * 2 * rs);
   L.status = take(nc * 4);
-  L.partials = take(2 * nc * static_cast<size_t>(L.n_wg_x) * nb * 8);   // two sets (mixing)
+  L.partials = take(2 * nc * static_cast<size_t>(L.n_wg_max) * nb * 8);   // two sets (mixing)
   L.ratio = take(nc * nb * 8);
   L.tobs = take(nc * static_cast<size_t>(sh.ztiles));
   L.coef = take(nc * 2 * m * rs);
@@ -206,13 +216,16 @@ struct mf_problem {
   WienerRun wiener;
   DiagRec diag;
   std::vector<int> obs_tiles;   // per chain: z-pass tiles holding an observed voxel
+  int xpath;                    // XPath of Gibbs sweeps
+  int n_wg(int path) const { return path == kPathSplit ? L.n_wg_split : L.n_wg_whole; }
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
 
 namespace {
 
 template <typename R>
-mf::SweepArgs<R> args_of(const mf_problem* p) {
+mf::SweepArgs<R> args_of(const mf_problem* p, int path = -1) {
+  if (path < 0) path = p->xpath;
   mf::SweepArgs<R> a{};
   char* ws = p->ws;
   a.spec = reinterpret_cast<mf::cx<R>*>(ws + p->L.spec);
@@ -224,7 +237,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   a.pk = reinterpret_cast<double*>(ws + p->L.pk);
   a.table = reinterpret_cast<R*>(ws + p->L.table);
   a.partials = reinterpret_cast<double*>(ws + p->L.partials);
-  a.partials2 = a.partials + static_cast<size_t>(p->desc.n_chains) * p->L.n_wg_x * p->desc.n_bins;
+  a.partials2 = a.partials + static_cast<size_t>(p->desc.n_chains) * p->L.n_wg_max * p->desc.n_bins;
   a.ratio = reinterpret_cast<double*>(ws + p->L.ratio);
   a.qthr = reinterpret_cast<const int32_t*>(ws + p->L.qthr);
   a.counts = reinterpret_cast<const double*>(ws + p->L.counts);
@@ -234,7 +247,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p) {
   a.spec_stride = p->L.spec_stride;
   a.m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
   a.nb = p->desc.n_bins;
-  a.n_wg_x = p->L.n_wg_x;
+  a.n_wg_x = p->n_wg(path);
   a.staging_chain = 0;
   a.sample_pk = p->desc.sample_pk;
   a.chain0 = p->desc.chain_id;
@@ -259,13 +272,14 @@ enum KernelId {
 };
 
 template <typename R, int N>
-void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
+void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool whole) {
   using ZT = mf::ZTile<R, N>;
   using YT = mf::YTile<R, N>;
   using XT = mf::XTile<R, N>;
   using YS = mf::YSTile<R, N>;
   using XS = mf::XSTile<R, N>;
-  constexpr bool split = mf::split_x<N>();
+  constexpr bool can_split = mf::split_x<N>();
+  const bool split = can_split && !whole;
   const dim3 zgrid(N / ZT::P, N / ZT::IXB, nch), zgrid1(N / ZT::P, N / ZT::IXB, 1);
   const size_t tables = 2 * a.nb * sizeof(R) + (a.nb + 1) * 4;
   switch (id) {
@@ -285,34 +299,39 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       hipLaunchKernelGGL((mf::zpass_kernel<R, N, mf::kZAccum>), zgrid, dim3(ZT::NT), 0, st, a);
       break;
     case kYF:
-      if constexpr (split)
-        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 / YS::G * (N / 2 + 1), 1, nch),
-                           dim3(YS::NT), 0, st, a);
-      else
-        hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), dim3((N / 2 + 1) * N / YT::NPEN, 1, nch),
-                           dim3(YT::NT), 0, st, a);
+      if constexpr (can_split) {
+        if (split) {
+          hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 / YS::G * (N / 2 + 1), 1, nch),
+                             dim3(YS::NT), 0, st, a);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((mf::ypass_kernel<R, N, false>), dim3((N / 2 + 1) * N / YT::NPEN, 1, nch),
+                         dim3(YT::NT), 0, st, a);
       break;
     case kYI:
-      if constexpr (split)
-        hipLaunchKernelGGL((mf::ysplit_kernel<R, N, true>),
-                           dim3(16 / YS::G * (N / 2 + 1) + a.nb, 1, nch),
-                           dim3(YS::NT), 0, st, a);
-      else
-        hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>),
-                           dim3((N / 2 + 1) * N / YT::NPEN + a.nb, 1, nch), dim3(YT::NT), 0, st, a);
+      if constexpr (can_split) {
+        if (split) {
+          hipLaunchKernelGGL((mf::ysplit_kernel<R, N, true>),
+                             dim3(16 / YS::G * (N / 2 + 1) + a.nb, 1, nch), dim3(YS::NT), 0, st, a);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((mf::ypass_kernel<R, N, true>),
+                         dim3((N / 2 + 1) * N / YT::NPEN + a.nb, 1, nch), dim3(YT::NT), 0, st, a);
       break;
     case kXDetK:
-      if constexpr (split)
+      if constexpr (can_split)
         hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet>), dim3(N / XS::P, N / 2 + 1, nch),
                            dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kXMixK:
-      if constexpr (split)
+      if constexpr (can_split)
         hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXMix>), dim3(N / XS::P, N / 2 + 1, nch),
                            dim3(XS::NT), 2 * XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kXMixInvK:
-      if constexpr (split)
+      if constexpr (can_split)
         hipLaunchKernelGGL((mf::xmixinv_kernel<R, N>), dim3(N / XS::P, N / 2 + 1, nch), dim3(XS::NT),
                            a.nb * sizeof(R) + (a.nb + 1) * 4, st, a);
       break;
@@ -320,17 +339,20 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
       hipLaunchKernelGGL((mf::mix_pk_kernel<R>), dim3(a.nb, nch), dim3(256), 0, st, a);
       break;
     case kXAdjK:
-      if constexpr (split)
+      if constexpr (can_split)
         hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXAdj>), dim3(N / XS::P, N / 2 + 1, nch),
                            dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kX:
-      if constexpr (split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample>), dim3(N / XS::P, N / 2 + 1, nch),
-                           dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
-      else
-        hipLaunchKernelGGL((mf::xpass_kernel<R, N>), dim3(N / XT::P, N / 2 + 1, nch), dim3(XT::NT),
-                           XT::NHIST * a.nb * sizeof(double) + tables, st, a);
+      if constexpr (can_split) {
+        if (split) {
+          hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample>), dim3(N / XS::P, N / 2 + 1, nch),
+                             dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((mf::xpass_kernel<R, N>), dim3(N / XT::P, N / 2 + 1, nch), dim3(XT::NT),
+                         XT::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kTable:
       hipLaunchKernelGGL((mf::pk_table_kernel<R>), dim3((a.nb + 63) / 64, nch), dim3(64), 0, st, a);
@@ -339,31 +361,36 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
 }
 
 template <typename R>
-void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st) {
+void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st, bool whole = false) {
   switch (n) {
-    case 8: launch_n<R, 8>(id, a, nch, st); break;
-    case 16: launch_n<R, 16>(id, a, nch, st); break;
-    case 32: launch_n<R, 32>(id, a, nch, st); break;
-    case 48: launch_n<R, 48>(id, a, nch, st); break;
-    case 64: launch_n<R, 64>(id, a, nch, st); break;
-    case 80: launch_n<R, 80>(id, a, nch, st); break;
-    case 96: launch_n<R, 96>(id, a, nch, st); break;
-    case 128: launch_n<R, 128>(id, a, nch, st); break;
-    case 256: launch_n<R, 256>(id, a, nch, st); break;
-    case 512: launch_n<R, 512>(id, a, nch, st); break;
+    case 8: launch_n<R, 8>(id, a, nch, st, whole); break;
+    case 16: launch_n<R, 16>(id, a, nch, st, whole); break;
+    case 32: launch_n<R, 32>(id, a, nch, st, whole); break;
+    case 48: launch_n<R, 48>(id, a, nch, st, whole); break;
+    case 64: launch_n<R, 64>(id, a, nch, st, whole); break;
+    case 80: launch_n<R, 80>(id, a, nch, st, whole); break;
+    case 96: launch_n<R, 96>(id, a, nch, st, whole); break;
+    case 128: launch_n<R, 128>(id, a, nch, st, whole); break;
+    case 256: launch_n<R, 256>(id, a, nch, st, whole); break;
+    case 512: launch_n<R, 512>(id, a, nch, st, whole); break;
   }
 }
 
-mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t st) {
+// path < 0: the problem's Gibbs-sweep path.
+mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t st, int path = -1,
+                         int pk_mode = mf::kPkDraw) {
   const int nch = p->desc.n_chains;
+  if (path < 0) path = p->xpath;
   if (p->fp64()) {
-    auto a = args_of<double>(p);
+    auto a = args_of<double>(p, path);
     a.staging_chain = staging_chain;
-    launch<double>(id, a, p->desc.n, nch, st);
+    a.pk_mode = pk_mode;
+    launch<double>(id, a, p->desc.n, nch, st, path == kPathWhole);
   } else {
-    auto a = args_of<float>(p);
+    auto a = args_of<float>(p, path);
     a.staging_chain = staging_chain;
-    launch<float>(id, a, p->desc.n, nch, st);
+    a.pk_mode = pk_mode;
+    launch<float>(id, a, p->desc.n, nch, st, path == kPathWhole);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MF_E_DEVICE, "kernel %d launch failed: %s", id, hipGetErrorString(e));
@@ -554,6 +581,7 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
   p->ws = static_cast<char*>(workspace);
   p->tau = tau;
   p->sweep = 0;
+  p->xpath = (n >= 32 && n <= 256) ? kPathSplit : kPathWhole;
   hipStream_t hs = static_cast<hipStream_t>(stream);
 
   auto cleanup = [&](mf_status r) {
@@ -570,7 +598,8 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
       hipMemcpyAsync(p->ws + L.tau, tau.data(), nch * 8, hipMemcpyHostToDevice, hs) != hipSuccess ||
       hipMemsetAsync(p->ws + L.status, 0, nch * 4, hs) != hipSuccess ||
       hipMemsetAsync(p->ws + L.ctr, 0, 8, hs) != hipSuccess ||
-      hipMemsetAsync(p->ws + L.partials, 0, static_cast<size_t>(nch) * L.n_wg_x * nb * 8, hs) != hipSuccess ||
+      hipMemsetAsync(p->ws + L.partials, 0, 2 * static_cast<size_t>(nch) * L.n_wg_max * nb * 8, hs) !=
+          hipSuccess ||
       hipStreamSynchronize(hs) != hipSuccess)
     return cleanup(fail(MF_E_DEVICE, "uploading tables failed"));
   // messenger coefficients in FP64 (alpha = 1 - tau/N, beta = tau d / N),
@@ -621,23 +650,10 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
   const int ids[6] = {kZ, kYF, kXMixK, kMixPkK, kXMixInvK, kYI};
   for (int i = 0; i < n_sweeps; ++i) {
     for (int id : ids) {
-      mf_status st;
-      if (id == kYI) {   // P and its table were set by the Metropolis-Hastings move
-        const int nch = p->desc.n_chains;
-        if (p->fp64()) {
-          auto a = args_of<double>(p);
-          a.pk_mode = mf::kPkNone;
-          launch<double>(id, a, p->desc.n, nch, hs);
-        } else {
-          auto a = args_of<float>(p);
-          a.pk_mode = mf::kPkNone;
-          launch<float>(id, a, p->desc.n, nch, hs);
-        }
-        const hipError_t e = hipGetLastError();
-        st = e == hipSuccess ? MF_OK : fail(MF_E_DEVICE, "launch failed: %s", hipGetErrorString(e));
-      } else {
-        st = launch_checked(p, id, 0, hs);
-      }
+      // the split path throughout; the inverse y-pass leaves P alone (the
+      // Metropolis-Hastings move has set it and its table)
+      const mf_status st = launch_checked(p, id, 0, hs, kPathSplit,
+                                          id == kYI ? mf::kPkNone : mf::kPkDraw);
       if (st != MF_OK) return st;
     }
     ++p->sweep;
@@ -786,10 +802,79 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
   return write_counter(p, h.sweep, hs);
 }
 
+mf_status mf_set_x_path(mf_problem* p, int32_t path) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (path != kPathSplit && path != kPathWhole) return fail(MF_E_INVALID_ARG, "unknown path %d", path);
+  if (path == kPathSplit && (p->desc.n < 32 || p->desc.n > 256))
+    return fail(MF_E_UNSUPPORTED_SIZE, "the split x transform needs 32 <= N <= 256");
+  p->xpath = path;
+  return MF_OK;
+}
+
+mf_status mf_get_x_path(const mf_problem* p, int32_t* path) {
+  if (!p || !path) return fail(MF_E_INVALID_ARG, "NULL argument");
+  *path = p->xpath;
+  return MF_OK;
+}
+
+mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, int32_t* path_out) {
+  if (!p || !ms || !path_out) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (trials < 1) return fail(MF_E_INVALID_ARG, "need at least one trial sweep");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  ms[kPathSplit] = ms[kPathWhole] = std::numeric_limits<double>::quiet_NaN();
+  const bool can_split = p->desc.n >= 32 && p->desc.n <= 256;
+  if (!can_split) {
+    p->xpath = kPathWhole;
+    *path_out = kPathWhole;
+    return MF_OK;
+  }
+  // Save every chain (spectrum, P, sweep index) and switch recording off, so
+  // the trial sweeps leave no trace.
+  const size_t cb = checkpoint_bytes(p);
+  std::vector<std::vector<char>> saved(p->desc.n_chains, std::vector<char>(cb));
+  mf_status st = MF_OK;
+  for (int c = 0; c < p->desc.n_chains && st == MF_OK; ++c)
+    st = mf_save_checkpoint(p, c, saved[c].data(), cb, stream);
+  if (st != MF_OK) return st;
+  const DiagRec diag = p->diag;
+  const int path0 = p->xpath;
+  p->diag = DiagRec{};
+  hipEvent_t e0, e1;
+  MF_HIP(hipEventCreate(&e0));
+  MF_HIP(hipEventCreate(&e1));
+  for (int path : {kPathSplit, kPathWhole}) {
+    p->xpath = path;
+    if ((st = mf_gibbs_sweep(p, 1, stream)) != MF_OK) break;   // warm-up
+    (void)hipEventRecord(e0, hs);
+    if ((st = mf_gibbs_sweep(p, trials, stream)) != MF_OK) break;
+    (void)hipEventRecord(e1, hs);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      st = fail(MF_E_DEVICE, "autotune timing failed");
+      break;
+    }
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    ms[path] = t / trials;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->diag = diag;
+  p->xpath = path0;
+  for (int c = 0; c < p->desc.n_chains; ++c) {
+    const mf_status r = mf_load_checkpoint(p, c, saved[c].data(), cb, stream);
+    if (st == MF_OK) st = r;
+  }
+  if (st != MF_OK) return st;
+  p->xpath = ms[kPathWhole] < ms[kPathSplit] ? kPathWhole : kPathSplit;
+  *path_out = p->xpath;
+  return MF_OK;
+}
+
 mf_status mf_sweep_bytes(const mf_problem* p, size_t* bytes) {
   if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
   const size_t rs = p->fp64() ? 8 : 4, n = p->desc.n, m = n * n * n, nb = p->desc.n_bins;
-  const size_t spec = (n / 2 + 1) * n * n * 2 * rs, part = static_cast<size_t>(p->L.n_wg_x) * nb * 8;
+  const size_t spec = (n / 2 + 1) * n * n * 2 * rs;
+  const size_t part = static_cast<size_t>(p->n_wg(p->xpath)) * nb * 8;
   for (int k = 0; k < MF_NUM_KERNELS; ++k) bytes[k] = 0;
   for (int c = 0; c < p->desc.n_chains; ++c) {
     const size_t coef = 2 * m * rs * static_cast<size_t>(p->obs_tiles[c]) / p->sh.ztiles;
@@ -994,7 +1079,7 @@ void with_n(int n, F&& f) {
 // spectrum `spec` (one chain, grid z = 1).
 template <typename R>
 mf::SweepArgs<R> wiener_args(const mf_problem* p, int chain, char* g, const WLayout& W) {
-  mf::SweepArgs<R> a = args_of<R>(p);
+  mf::SweepArgs<R> a = args_of<R>(p, kPathSplit);
   a.coef = reinterpret_cast<const R*>(g + W.wcoef);
   a.table = reinterpret_cast<R*>(g + W.table);
   a.pk = reinterpret_cast<double*>(g + W.pkg);

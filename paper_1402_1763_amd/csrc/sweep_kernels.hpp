@@ -118,24 +118,26 @@ struct ZTile {
   using TL = Tile<N, NPEN, NT, true, PSTR, 0>;
 };
 
-// y-pass: NPEN consecutive contiguous pencils, q-fastest, padded LDS.
+// y-pass (whole-transform path): NPEN consecutive contiguous pencils of one
+// kz plane, q-fastest, padded LDS.
 template <typename R, int N>
 struct YTile {
-  static constexpr int EPT = 16;
+  static constexpr int EPT = ept<N>();
   static constexpr int CAP = sizeof(R) == 4 ? 4096 : 2048;
-  static constexpr int NPEN = CAP / N > N ? N : CAP / N;
+  static constexpr int NPEN = divisor_below(N, CAP / N);
   static constexpr int NT = NPEN * N / EPT;
   static constexpr int PADS = ilog2(Radices<N>::r[0]);
   static constexpr int PSTR = N + (N >> PADS);
   using TL = Tile<N, NPEN, NT, false, PSTR, PADS>;
 };
 
-// x-pass: one kz plane, P consecutive iy columns, pencil-fastest.
+// x-pass (whole-transform path): one kz plane, P consecutive iy columns,
+// pencil-fastest.
 template <typename R, int N>
 struct XTile {
-  static constexpr int EPT = 16;
+  static constexpr int EPT = ept<N>();
   static constexpr int CAP = 4096;
-  static constexpr int P = CAP / N > N ? N : CAP / N;
+  static constexpr int P = divisor_below(N, CAP / N);
   static constexpr int NT = P * N / EPT;
   static constexpr int PSTR = N + 1;
   static constexpr int NWAVES = (NT + 63) / 64;
@@ -1064,7 +1066,8 @@ xmixinv_kernel(SweepArgs<R> a) {
   for (int j = 0; j < 16; ++j) base[static_cast<size_t>(j) * N] = v[j];
 }
 
-// Whole-transform x-pass (N = 8, 16, 512): workgroup = one kz plane and P
+// Whole-transform x-pass (the only path for N = 8, 16, 512; the alternative
+// to the split path elsewhere): workgroup = one kz plane and P
 // consecutive iy columns; forward x-DFT, draw, inverse x-DFT (in the reversed
 // radix order, so it starts from the same registers).
 template <typename R, int N>

@@ -1,0 +1,105 @@
+"""GPU tests of the two x-transform paths (split and whole pencils) and of the
+autotuner that chooses between them."""
+import numpy as np
+import pytest
+
+from oracle import mixing, sampler
+from paper_1402_1763_amd import binding, workloads
+from tests.gpu_util import TOL, errors, gpu_sampler, oracle_problem, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.load()
+    torch.cuda.set_device(0)
+
+
+@pytest.mark.parametrize("precision,n", [("fp64", 32), ("fp32", 48), ("fp64", 64), ("fp32", 80),
+                                         ("fp32", 96), ("fp64", 128)])
+def test_whole_path_matches_oracle(precision, n):
+    w = workloads.small_workload(n, 8, precision=precision, seed=91, rng_seed=92)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    smp.set_x_path("whole")
+    assert smp.x_path() == "whole"
+    print(f"whole path n={n} {precision}", flush=True)
+    smp.sweep(4)
+    s_gpu, p_gpu, _ = smp.state()
+    s_ref, p_ref = run_oracle(w, pb, 4)
+    err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+    print(f"  err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
+    assert err_s < TOL[precision] and err_p < TOL[precision]
+
+
+def test_paths_agree_at_256():
+    w = workloads.SURVEY_256_MIXED
+    pb = workloads.make_problem(w)
+    out = []
+    for path in ("split", "whole"):
+        smp = gpu_sampler(w, pb)
+        smp.set_x_path(path)
+        smp.sweep(2)
+        out.append(smp.state()[:2])
+        smp.close()
+    err_s, err_p = errors(out[1][0], out[1][1], out[0][0], out[0][1])
+    print(f"256^3 split vs whole: err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
+    assert err_s < 2e-5 and err_p < 2e-5
+
+
+def test_switching_paths_mid_chain_matches_oracle():
+    w = workloads.small_workload(64, 8, precision="fp64", seed=93, rng_seed=94)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    for path in ("split", "whole", "split", "whole"):
+        smp.set_x_path(path)
+        smp.sweep(1)
+    smp.mixing_sweep(1)          # always on the split path
+    s_gpu, p_gpu, _ = smp.state()
+    prob = oracle_problem(w, pb)
+    st = sampler.State(s=np.zeros((w.n,) * 3), p_grid=pb["pk_init"] / w.cell_volume)
+    st = sampler.run_chain(prob, st, 4)
+    st = mixing.mixing_sweep(prob, st)
+    err_s, err_p = errors(s_gpu, p_gpu, st.s, st.p_grid * w.cell_volume)
+    assert err_s < TOL["fp64"] and err_p < TOL["fp64"]
+
+
+def test_autotune_keeps_the_chain_and_picks_a_path():
+    w = workloads.small_workload(64, 8, precision="fp32", seed=95, rng_seed=96)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    smp.set_diagnostics(start=0, thin=1, trace_cap=16, moments=True)
+    smp.sweep(3)
+    s0, p0, n0 = smp.state()
+    rec0 = smp.recorded()
+    res = smp.autotune(trials=3)
+    print("autotune", res, flush=True)
+    assert res["path"] in ("split", "whole") and smp.x_path() == res["path"]
+    assert all(np.isfinite(v) and v > 0 for v in res["ms"].values())
+    s1, p1, n1 = smp.state()
+    assert np.array_equal(s0, s1) and np.array_equal(p0, p1) and n0 == n1
+    assert smp.recorded() == rec0
+    smp.sweep(2)
+    # the tuned chain equals an untuned one that ran its first three sweeps on
+    # the default path and the last two on the chosen one
+    ref2 = gpu_sampler(w, pb)
+    ref2.sweep(3)
+    ref2.set_x_path(res["path"])
+    ref2.sweep(2)
+    assert np.array_equal(smp.state()[0], ref2.state()[0])
+
+
+def test_path_errors_and_small_grids():
+    w = workloads.small_workload(16, 4, precision="fp32")
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    assert smp.x_path() == "whole"
+    with pytest.raises(binding.MFError) as e:
+        smp.set_x_path("split")
+    assert e.value.status == binding.MF_E_UNSUPPORTED_SIZE
+    res = smp.autotune(trials=1)
+    assert res["path"] == "whole" and np.isnan(res["ms"]["split"])
