@@ -98,7 +98,7 @@ def bench_batched(args):
         pbs = [workloads.make_problem(w) for w in ws]
         samplers.append(binding.Sampler([pb["data"] for pb in pbs], [pb["noise_var"] for pb in pbs],
                                         [pb["pk_init"] for pb in pbs], 16, ws[0].box,
-                                        seed=ws[0].rng_seed, precision="fp32"))
+                                        seed=ws[0].rng_seed, chain_id=1000 * n, precision="fp32"))
         chain_voxels += chains * n ** 3
         sweep_bytes += sum(samplers[-1].sweep_bytes().values())
     tuned = {}
@@ -127,6 +127,28 @@ def bench_batched(args):
         _, pk, _ = smp.state(want_s=False)
         assert np.all(np.isfinite(pk))
     graph.close()
+    # the plain way: every chain its own single-chain problem, swept in turn
+    singles = []
+    for n, chains in workloads.BATCHED_SIZES:
+        for c in range(chains):
+            wc = workloads.batched_chain(n, c)
+            pc = workloads.make_problem(wc)
+            singles.append(binding.Sampler(pc["data"], pc["noise_var"], pc["pk_init"], 16, wc.box,
+                                           seed=wc.rng_seed, chain_id=1000 * n + c,
+                                           precision="fp32"))
+    plain_steps = max(1, args.steps // 10)
+    for smp in singles:
+        smp.sweep(2)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(plain_steps):
+        for smp in singles:
+            smp.sweep(1)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = start.elapsed_time(stop) / plain_steps
+    for smp in singles:
+        smp.close()
     chains = sum(c for _, c in workloads.BATCHED_SIZES)
     out = {
         "metric": "batched Gibbs sweeps/s (56 independent chains of sides 48-96, one graph replay each)",
@@ -142,9 +164,51 @@ def bench_batched(args):
                    "sweep_bytes_algorithmic": sweep_bytes,
                    "sweep_hbm_frac": round(sweep_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                    "eager_ms_per_step": round(ms_eager, 5),
-                   "graph_speedup_vs_eager": round(ms_eager / ms, 3)},
+                   "graph_speedup_vs_eager": round(ms_eager / ms, 3),
+                   "plain_single_chain_ms_per_step": round(ms_plain, 5),
+                   "speedup_vs_plain_single_chain_sweeps": round(ms_plain / ms, 3)},
     }
     print(json.dumps(out), flush=True)
+
+
+def fp64_sweep_rate(w, pb, steps: int) -> float:
+    """Plain FP64 sweeps/s of the same problem on the same GPU (after a
+    warm-up and the path autotuner)."""
+    import torch
+
+    from paper_1402_1763_amd import binding
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision="fp64")
+    smp.autotune(trials=5)
+    smp.sweep(5)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    smp.sweep(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    smp.close()
+    return round(1000.0 * steps / start.elapsed_time(stop), 2)
+
+
+def plain_sweep_ms(w, pb, steps: int, precision: str = "fp32") -> float:
+    """ms per plain Gibbs sweep of one problem on this GPU."""
+    import torch
+
+    from paper_1402_1763_amd import binding
+    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision=precision)
+    smp.sweep(5)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    smp.sweep(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    smp.close()
+    return start.elapsed_time(stop) / steps
 
 
 def bench_mixing(args):
@@ -252,6 +316,7 @@ def bench_wiener(args):
     torch.cuda.synchronize()
     fwd_ms, bwd_ms = start.elapsed_time(mid), mid.elapsed_time(stop)
     assert np.isfinite(float(chi2)) and bool(torch.isfinite(gp).all())
+    gibbs_ms = plain_sweep_ms(w, pb, 200)
     spec = 8 * (w.n // 2 + 1) * w.n ** 2
     coef_frac = (smp.sweep_bytes()["zpass"] - 2 * spec) / (8 * w.m)
     nbytes = wiener_grad_bytes(w.n, 4, w.n_bins, n_iter, every, coef_frac)
@@ -266,6 +331,8 @@ def bench_wiener(args):
                    "iterations": n_iter, "ckpt_every": every,
                    "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
                    "iterations_per_s": round(3 * n_iter * 1000.0 / ms, 1),
+                   "plain_gibbs_sweep_ms": round(gibbs_ms, 5),
+                   "iteration_cost_vs_gibbs_sweep": round(ms / (3 * n_iter) / gibbs_ms, 3),
                    "bytes_algorithmic": nbytes,
                    "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
@@ -305,6 +372,8 @@ def main():
     ap.add_argument("--workload", default="gibbs-256^3-fp32-survey")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip timing the same problem's FP64 sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (calibrates "
                          "the HBM byte counters) and exit")
@@ -380,6 +449,7 @@ def main():
                     "algorithmic_bytes": alg,
                     "kernel_ms": {k: round(v, 5) for k, v in kernel_ms.items()}}
     smp.close()
+    fp64 = None if args.no_fp64_compare else fp64_sweep_rate(w, pb, min(args.steps, 100))
 
     out = {
         "metric": "Gibbs sweeps/s at 256^3 FP32 (and % HBM roofline) vs plain FP64 sweep",
@@ -407,7 +477,10 @@ def main():
                    "sweep_hbm_frac_5pass_bytes": round(48.25 * w.m * real_bytes / 4
                                                        / (ms_per_step * 1e-3) / 1e9
                                                        / HBM_PEAK_GBS, 4),
-                   "wall_s_timed_region": round(wall_s, 4)},
+                   "wall_s_timed_region": round(wall_s, 4),
+                   "fp64_sweeps_per_s": fp64,
+                   "speedup_vs_fp64_sweep": (round(1000.0 / ms_per_step / fp64, 3)
+                                             if fp64 else None)},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
