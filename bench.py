@@ -211,6 +211,66 @@ def plain_sweep_ms(w, pb, steps: int, precision: str = "fp32") -> float:
     return start.elapsed_time(stop) / steps
 
 
+def bench_chain_efficiency(args):
+    """Statistical efficiency on the 128^3 survey problem (Sec. 4.3): after a
+    burn-in, record every 10th of `steps` sweeps of P(k) and compute the
+    autocorrelation and the ten-percent correlation length n_c of every bin,
+    for Gibbs sweeps and for mixing sweeps (Alg. 3)."""
+    import torch
+
+    from paper_1402_1763_amd import binding, workloads
+    torch.cuda.set_device(0)
+    w = workloads.SURVEY_128_FP32
+    pb = workloads.make_problem(w)
+    thin, burn = 10, args.warmup
+    cap = args.steps // thin
+    truth = workloads.power_spectrum(workloads.bin_centres(w), w)
+    out_runs = {}
+    for kind in ("gibbs", "mixing", "alternating"):
+        smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                              seed=w.rng_seed, precision="fp32")
+
+        def alternate(n, smp=smp):
+            for i in range(n):
+                (smp.sweep if i % 2 == 0 else smp.mixing_sweep)(1)
+
+        step = {"gibbs": smp.sweep, "mixing": smp.mixing_sweep, "alternating": alternate}[kind]
+        step(burn)
+        smp.set_diagnostics(start=burn, thin=thin, trace_cap=cap)
+        stream = torch.cuda.current_stream()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        step(args.steps)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.steps
+        trace = smp.trace()
+        max_lag = min(cap - 1, 400)
+        _, nc = binding.acf(trace, max_lag)
+        mean_pk = trace.mean(dim=0).cpu().numpy()
+        ncv = nc.cpu().numpy()
+        out_runs[kind] = {"sweeps_per_s": round(1000.0 / ms, 1),
+                          "n_c_recorded": [int(v) for v in ncv],
+                          "bins_with_n_c_le_50": int(np.sum((ncv >= 0) & (ncv <= 50))),
+                          "posterior_mean_over_truth": [round(float(v), 3)
+                                                        for v in mean_pk / truth]}
+        smp.close()
+    best = max(out_runs, key=lambda k: out_runs[k]["bins_with_n_c_le_50"])
+    out = {
+        "metric": "share of P(k) bins with correlation length n_c <= 50 recorded samples "
+                  "(ten-percent rule, every 10th sweep) at 128^3 FP32",
+        "value": round(out_runs[best]["bins_with_n_c_le_50"] / w.n_bins, 4),
+        "unit": "fraction of bins", "n_gpus": 1, "steps": args.steps, "warmup": burn,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "chain-efficiency-128^3-fp32-survey", "thin": thin,
+                   "recorded": cap, "bins": w.n_bins, "max_lag": min(cap - 1, 400),
+                   "best_sampler": best, **out_runs},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_mixing(args):
     """Mixing sweeps (Sec. 3.3, shell form) on the 256^3 survey problem."""
     import torch
@@ -404,6 +464,8 @@ def main():
         return bench_wiener(args)
     if args.workload == "mixing-256^3-fp32-survey":
         return bench_mixing(args)
+    if args.workload == "chain-efficiency-128^3-fp32-survey":
+        return bench_chain_efficiency(args)
     w = workloads.WORKLOADS[args.workload]
     pb = workloads.make_problem(w)
     torch.cuda.set_device(0)
