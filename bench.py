@@ -339,21 +339,31 @@ def wiener_grad_bytes(n: int, real_bytes: int, n_bins: int, n_iter: int, every: 
     return n_iter * (plain + store + adjoint) + forward_extra + backward_extra
 
 
-def bench_wiener(args):
+def bench_wiener(args, chains: int = 1):
     """chi2 of the messenger Wiener filter and its gradient with respect to P
-    and d: 128^3 survey problem, 32 bins, 50 iterations, checkpoint every 10."""
+    and d: 128^3 survey problem, 32 bins, 50 iterations, checkpoint every 10;
+    with chains > 1, that many data sets (seeds) of the same survey in one
+    launch per pass."""
     import torch
 
     from paper_1402_1763_amd import binding, workloads
     torch.cuda.set_device(0)
     w = workloads.SURVEY_128_FP32
     n_iter, every = 50, 10
-    pb = workloads.make_problem(w)
-    smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+    pbs = [workloads.make_problem(w, seed=w.seed + 17 * c) for c in range(chains)]
+    pb = pbs[0]
+    smp = binding.Sampler([q["data"] for q in pbs], [q["noise_var"] for q in pbs],
+                          [q["pk_init"] for q in pbs], w.n_bins, w.box,
                           seed=w.rng_seed, precision="fp32", sample_pk=False)
-    pk = torch.from_numpy(workloads.power_spectrum(workloads.bin_centres(w), w)).cuda()
-    d = torch.from_numpy(pb["data"]).cuda()
-    wf = binding.WienerFilter(smp, n_iter, every)
+    pk1 = workloads.power_spectrum(workloads.bin_centres(w), w)
+    if chains == 1:
+        pk = torch.from_numpy(pk1).cuda()
+        d = torch.from_numpy(pb["data"]).cuda()
+        wf = binding.WienerFilter(smp, n_iter, every)
+    else:
+        pk = torch.from_numpy(np.stack([pk1] * chains)).cuda()
+        d = torch.from_numpy(np.stack([q["data"] for q in pbs])).cuda()
+        wf = binding.WienerFilter(smp, n_iter, every, chain=None)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         wf.forward(d, pk)
@@ -375,28 +385,28 @@ def bench_wiener(args):
     stop.record(stream)
     torch.cuda.synchronize()
     fwd_ms, bwd_ms = start.elapsed_time(mid), mid.elapsed_time(stop)
-    assert np.isfinite(float(chi2)) and bool(torch.isfinite(gp).all())
+    assert bool(torch.isfinite(chi2).all()) and bool(torch.isfinite(gp).all())
     gibbs_ms = plain_sweep_ms(w, pb, 200)
     spec = 8 * (w.n // 2 + 1) * w.n ** 2
-    coef_frac = (smp.sweep_bytes()["zpass"] - 2 * spec) / (8 * w.m)
-    nbytes = wiener_grad_bytes(w.n, 4, w.n_bins, n_iter, every, coef_frac)
+    coef_frac = (smp.sweep_bytes()["zpass"] - 2 * spec * chains) / (8 * w.m * chains)
+    nbytes = chains * wiener_grad_bytes(w.n, 4, w.n_bins, n_iter, every, coef_frac)
     out = {
         "metric": "messenger Wiener-filter chi2 + gradient evaluations/s (128^3, 50 iterations, "
-                  "checkpoint every 10)",
-        "value": round(1000.0 / ms, 2), "unit": "evaluations/s", "n_gpus": 1,
+                  "checkpoint every 10)" + (f", {chains} data sets per launch" if chains > 1 else ""),
+        "value": round(chains * 1000.0 / ms, 2), "unit": "evaluations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "wiener-grad-128^3-fp32-survey", "n": w.n, "n_bins": w.n_bins,
+        "config": {"workload": args.workload, "n": w.n, "n_bins": w.n_bins, "chains": chains,
                    "iterations": n_iter, "ckpt_every": every,
                    "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
-                   "iterations_per_s": round(3 * n_iter * 1000.0 / ms, 1),
+                   "iterations_per_s": round(3 * n_iter * chains * 1000.0 / ms, 1),
                    "plain_gibbs_sweep_ms": round(gibbs_ms, 5),
-                   "iteration_cost_vs_gibbs_sweep": round(ms / (3 * n_iter) / gibbs_ms, 3),
+                   "iteration_cost_vs_gibbs_sweep": round(ms / (3 * n_iter * chains) / gibbs_ms, 3),
                    "bytes_algorithmic": nbytes,
                    "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and chains == 1:
         out["cpu_baseline"] = wiener_cpu_baseline(w, pb, n_iter)
     print(json.dumps(out), flush=True)
 
@@ -462,6 +472,8 @@ def main():
         return bench_batched(args)
     if args.workload == "wiener-grad-128^3-fp32-survey":
         return bench_wiener(args)
+    if args.workload == "wiener-grad-128^3-x8-fp32-survey":
+        return bench_wiener(args, chains=8)
     if args.workload == "mixing-256^3-fp32-survey":
         return bench_mixing(args)
     if args.workload == "chain-efficiency-128^3-fp32-survey":

@@ -240,35 +240,38 @@ void mf_graph_destroy(mf_graph* g);
  * s_0 = 0, K iterations give s_K, and the loss is
  *   chi2_K = sum_i d_i (d_i - s_K,i) / N_i   over observed voxels,
  * which tends to d^T (S + N)^-1 d as K grows.  The noise model (N_i, the
- * mask and tau) is chain `chain`'s; d and P are inputs of each call.
+ * mask and tau) is the chain's; d and P are inputs of each call.
  *
- * mf_wiener_workspace_bytes: size of the caller-owned device workspace for K
- *   iterations with a checkpoint every `ckpt_every`.  It holds ceil(K / E)
- *   checkpoints plus E stored spectra, about (ceil(K/E) + E + 6) * 8 M bytes
- *   in FP32 mode.
- * mf_wiener_forward: d (FP64, M, [ix][iy][iz]; ignored where unobserved) and
- *   pk (FP64, n_bins, physical units) are device arrays.  Writes chi2_K to
- *   the device double `chi2` and, when `s_out` (device FP64, M) is not NULL,
- *   s_K.  Checkpoints of s_k every `ckpt_every` iterations stay in the
- *   workspace for mf_wiener_backward.  The chain's Gibbs state is not
- *   touched.
+ * chain >= 0 selects one chain.  chain = -1 runs every chain of the problem
+ * in the same launches (arrays then hold the chains one after another).
+ *
+ * mf_wiener_workspace_bytes: size of the caller-owned device workspace for
+ *   that chain selection, K iterations and a checkpoint every `ckpt_every`.
+ *   Per chain it holds ceil(K / E) checkpoints plus E stored spectra, about
+ *   (ceil(K/E) + E + 6) * 8 M bytes in FP32 mode.
+ * mf_wiener_forward: d (FP64, M per chain, [ix][iy][iz]; ignored where
+ *   unobserved) and pk (FP64, n_bins per chain, physical units) are device
+ *   arrays.  Writes chi2_K to the device doubles `chi2` (one per chain) and,
+ *   when `s_out` (device FP64, M per chain) is not NULL, s_K.  Checkpoints of
+ *   s_k every `ckpt_every` iterations stay in the workspace for
+ *   mf_wiener_backward.  The chains' Gibbs state is not touched.
  * mf_wiener_backward: the gradient of the last forward run's chi2_K with
- *   respect to d (device FP64, M; zero where unobserved) and to P_b (device
- *   FP64, n_bins, physical units).  It takes the same d and the same
- *   workspace as that run and recomputes each segment from its checkpoint:
- *   2 K iterations.
+ *   respect to d (device FP64, M per chain; zero where unobserved) and to
+ *   P_b (device FP64, n_bins per chain, physical units).  It takes the same
+ *   chain selection, the same d and the same workspace as that run, and
+ *   recomputes each segment from its checkpoint: 2 K iterations.
  *
  * Both calls enqueue on `stream` without synchronising.  They use the
- * problem's state staging buffer and chain 0's shell partials as scratch, so
- * they must not overlap sweeps or state calls on the same problem.
+ * problem's state staging buffer and its shell partials as scratch, so they
+ * must not overlap sweeps or state calls on the same problem.
  * Errors:
  *  - MF_E_UNSUPPORTED_SIZE for grid sides outside 32..256;
  *  - MF_E_STATE for a bad chain, or a backward call without a matching
  *    forward run;
  *  - MF_E_WORKSPACE for a workspace that is too small or not aligned;
  *  - MF_E_INVALID_ARG, MF_E_DEVICE. */
-mf_status mf_wiener_workspace_bytes(const mf_problem* p, int32_t n_iter, int32_t ckpt_every,
-                                    size_t* bytes);
+mf_status mf_wiener_workspace_bytes(const mf_problem* p, int32_t chain, int32_t n_iter,
+                                    int32_t ckpt_every, size_t* bytes);
 mf_status mf_wiener_forward(mf_problem* p, int32_t chain, const double* d, const double* pk,
                             int32_t n_iter, int32_t ckpt_every, void* workspace, size_t ws_bytes,
                             double* chi2, double* s_out, void* stream);

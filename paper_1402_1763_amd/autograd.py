@@ -1,6 +1,7 @@
 """chi2_K of the messenger Wiener filter as a differentiable torch function.
 
-wiener_chi2(pk, d, wf) returns chi2_K = sum_obs d (d - s_K) / N, where s_K is
+wiener_chi2(pk, d, wf) returns chi2_K = sum_obs d (d - s_K) / N (one per chain
+when wf covers every chain of its sampler), where s_K is
 the K-th iterate of the deterministic messenger iteration from s = 0 (the
 means of the messenger and signal conditionals, Sec. 3.1) at power spectrum
 pk.  Its backward pass runs the library's checkpointed adjoint (one forward
@@ -33,6 +34,8 @@ class WienerChi2(torch.autograd.Function):
         if wf.generation != ctx.generation:   # checkpoints overwritten since
             wf.forward(d, pk)
         grad_d, grad_pk = wf.backward(d)
+        if grad_out.dim() == 1:        # one chi2 per chain
+            return grad_out[:, None] * grad_pk, grad_out[:, None, None, None] * grad_d, None
         return grad_out * grad_pk, grad_out * grad_d, None
 
 

@@ -86,7 +86,7 @@ SIGNATURES = {
     "mf_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mf_graph_destroy": (None, [ctypes.c_void_p]),
     "mf_wiener_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                                                 ctypes.POINTER(ctypes.c_size_t)]),
+                                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "mf_wiener_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -292,9 +292,9 @@ def mf_graph_destroy(graph: int):
         load().mf_graph_destroy(ctypes.c_void_p(graph))
 
 
-def mf_wiener_workspace_bytes(handle: int, n_iter: int, ckpt_every: int) -> int:
+def mf_wiener_workspace_bytes(handle: int, chain: int, n_iter: int, ckpt_every: int) -> int:
     out = ctypes.c_size_t(0)
-    _check(load().mf_wiener_workspace_bytes(ctypes.c_void_p(handle), n_iter, ckpt_every,
+    _check(load().mf_wiener_workspace_bytes(ctypes.c_void_p(handle), chain, n_iter, ckpt_every,
                                             ctypes.byref(out)))
     return out.value
 
@@ -489,33 +489,40 @@ class SweepGraph:
 
 
 class WienerFilter:
-    """The deterministic messenger Wiener filter of one chain of a Sampler
-    (its noise model: N, mask, tau), n_iter iterations from s = 0 with a
-    checkpoint every ckpt_every, and its adjoint.  d and pk are float64 cuda
-    tensors ((N, N, N) and (n_bins,), P in physical units)."""
+    """The deterministic messenger Wiener filter of a Sampler's chain (its
+    noise model: N, mask, tau), n_iter iterations from s = 0 with a
+    checkpoint every ckpt_every, and its adjoint.  chain=None runs every chain
+    of the sampler in the same launches.  d and pk are float64 cuda tensors:
+    (N, N, N) and (n_bins,) for one chain, with a leading chain axis for all
+    chains; P in physical units."""
 
-    def __init__(self, sampler: "Sampler", n_iter: int, ckpt_every: int, chain: int = 0):
+    def __init__(self, sampler: "Sampler", n_iter: int, ckpt_every: int, chain: Optional[int] = 0):
         import torch
-        self.sampler, self.n_iter, self.ckpt_every, self.chain = sampler, n_iter, ckpt_every, chain
-        self.ws_bytes = mf_wiener_workspace_bytes(sampler.handle, n_iter, ckpt_every)
+        self.sampler, self.n_iter, self.ckpt_every = sampler, n_iter, ckpt_every
+        self.chain = -1 if chain is None else chain
+        self.n_chains = sampler.n_chains if chain is None else 1
+        self.ws_bytes = mf_wiener_workspace_bytes(sampler.handle, self.chain, n_iter, ckpt_every)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
                                      device=sampler.workspace.device)
         self._ptr = (self.workspace.data_ptr() + 255) // 256 * 256
         self.generation = 0      # increments with every forward run
 
+    def _lead(self):
+        return () if self.chain >= 0 else (self.n_chains,)
+
     def _check_inputs(self, d, pk):
         import torch
         n, nb = self.sampler.n, self.sampler.n_bins
-        for name, t, shape in (("d", d, (n, n, n)), ("pk", pk, (nb,))):
+        for name, t, shape in (("d", d, self._lead() + (n, n, n)), ("pk", pk, self._lead() + (nb,))):
             if (t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape
                     or not t.is_contiguous()):
                 raise ValueError(f"{name} must be a contiguous float64 cuda tensor of shape {shape}")
 
     def forward(self, d, pk, want_s: bool = False):
-        """chi2_K as a 0-dim tensor, and s_K when want_s."""
+        """chi2_K (a 0-dim tensor, or one per chain), and s_K when want_s."""
         import torch
         self._check_inputs(d, pk)
-        chi2 = torch.empty((), dtype=torch.float64, device=d.device)
+        chi2 = torch.empty(self._lead(), dtype=torch.float64, device=d.device)
         s = torch.empty_like(d) if want_s else None
         mf_wiener_forward(self.sampler.handle, self.chain, d.data_ptr(), pk.data_ptr(),
                           self.n_iter, self.ckpt_every, self._ptr, self.ws_bytes,
@@ -528,7 +535,8 @@ class WienerFilter:
         """(d chi2/d d, d chi2/d pk) of the last forward run (same d)."""
         import torch
         grad_d = torch.empty_like(d)
-        grad_pk = torch.empty(self.sampler.n_bins, dtype=torch.float64, device=d.device)
+        grad_pk = torch.empty(self._lead() + (self.sampler.n_bins,), dtype=torch.float64,
+                              device=d.device)
         mf_wiener_backward(self.sampler.handle, self.chain, d.data_ptr(), self._ptr,
                            self.ws_bytes, grad_d.data_ptr(), grad_pk.data_ptr(),
                            self.sampler.stream.cuda_stream)

@@ -1010,50 +1010,68 @@ const char* mf_last_error(void) { return g_last_error.c_str(); }
 // ---------------------------------------------------------------- Wiener filter
 namespace {
 
-// Wiener workspace: scratch and per-run buffers, each 256-byte aligned.
+// Wiener workspace for nc chains processed together; every buffer holds the
+// chains one after another, each 256-byte aligned.
 struct WLayout {
   size_t partial, pkg, gacc, table, wcoef, fwd, adj, ckpt, aux, acc, total;
-  size_t spec_bytes;
-  int nblk, n_ckpt;
+  size_t spec_bytes;   // one chain's spectrum (with the problem's stride)
+  int nblk, n_ckpt, nc;
 };
 
-WLayout wiener_layout(const mf_problem* p, int n_iter, int every) {
+WLayout wiener_layout(const mf_problem* p, int n_iter, int every, int nc) {
   const size_t rs = p->fp64() ? 8 : 4;
   const size_t n = p->desc.n, m = n * n * n, nb = p->desc.n_bins;
   WLayout W{};
+  W.nc = nc;
   W.nblk = static_cast<int>((m / 2 + mf::kWienerThreads - 1) / mf::kWienerThreads);
   W.n_ckpt = (n_iter + every - 1) / every;
   W.spec_bytes = p->L.spec_stride * 2 * rs;
+  const size_t specs = static_cast<size_t>(nc) * W.spec_bytes;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
     off = align_up(off + bytes);
     return at;
   };
-  W.partial = take(static_cast<size_t>(W.nblk) * 8);
-  W.pkg = take(nb * 8);
-  W.gacc = take(nb * 8);
-  W.table = take(nb * 2 * rs);
-  W.wcoef = take(2 * m * rs);
-  W.fwd = take(W.spec_bytes);
-  W.adj = take(W.spec_bytes);
-  W.ckpt = take(static_cast<size_t>(W.n_ckpt) * W.spec_bytes);
-  W.aux = take(static_cast<size_t>(every) * W.spec_bytes);
-  W.acc = take(m * rs);
+  W.partial = take(static_cast<size_t>(nc) * W.nblk * 8);
+  W.pkg = take(nc * nb * 8);
+  W.gacc = take(nc * nb * 8);
+  W.table = take(nc * nb * 2 * rs);
+  W.wcoef = take(nc * 2 * m * rs);
+  W.fwd = take(specs);
+  W.adj = take(specs);
+  W.ckpt = take(static_cast<size_t>(W.n_ckpt) * specs);
+  W.aux = take(static_cast<size_t>(every) * specs);
+  W.acc = take(nc * m * rs);
   W.total = off;
   return W;
 }
 
+// chain = -1: all chains of the problem; else that one chain.
+mf_status wiener_chains(const mf_problem* p, int chain, int* c0, int* nc) {
+  if (chain == -1) {
+    *c0 = 0;
+    *nc = p->desc.n_chains;
+    return MF_OK;
+  }
+  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  *c0 = chain;
+  *nc = 1;
+  return MF_OK;
+}
+
 mf_status check_wiener(const mf_problem* p, int chain, int n_iter, int every, const void* gws,
-                       size_t gws_bytes, WLayout* W) {
+                       size_t gws_bytes, WLayout* W, int* c0) {
   if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
   if (p->desc.n < 32 || p->desc.n > 256)
     return fail(MF_E_UNSUPPORTED_SIZE, "the Wiener iteration supports grid sides 32 to 256 (got %d)",
                 p->desc.n);
-  if (chain < 0 || chain >= p->desc.n_chains) return fail(MF_E_STATE, "chain %d out of range", chain);
+  int nc = 0;
+  mf_status r = wiener_chains(p, chain, c0, &nc);
+  if (r != MF_OK) return r;
   if (n_iter < 1 || every < 1 || every > n_iter)
     return fail(MF_E_INVALID_ARG, "need n_iter >= 1 and 1 <= ckpt_every <= n_iter");
-  *W = wiener_layout(p, n_iter, every);
+  *W = wiener_layout(p, n_iter, every, nc);
   if (!gws || reinterpret_cast<uintptr_t>(gws) % kAlign != 0)
     return fail(MF_E_WORKSPACE, "Wiener workspace NULL or not 256-byte aligned");
   if (gws_bytes < W->total)
@@ -1075,20 +1093,23 @@ void with_n(int n, F&& f) {
   }
 }
 
-// Sweep arguments of one deterministic iteration of chain `chain` on the
-// spectrum `spec` (one chain, grid z = 1).
+// Sweep arguments of the deterministic iteration of chains c0 .. c0 + nc - 1
+// (grid z = nc; chain c of the launch is problem chain c0 + c).
 template <typename R>
-mf::SweepArgs<R> wiener_args(const mf_problem* p, int chain, char* g, const WLayout& W) {
+mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, char* g, const WLayout& W) {
   mf::SweepArgs<R> a = args_of<R>(p, kPathSplit);
   a.coef = reinterpret_cast<const R*>(g + W.wcoef);
   a.table = reinterpret_cast<R*>(g + W.table);
   a.pk = reinterpret_cast<double*>(g + W.pkg);
   a.gacc = reinterpret_cast<double*>(g + W.gacc);
-  a.tau = reinterpret_cast<const double*>(p->ws + p->L.tau) + chain;
-  a.status = reinterpret_cast<uint32_t*>(p->ws + p->L.status) + chain;
-  a.chain0 = p->desc.chain_id + chain;
+  a.tau = reinterpret_cast<const double*>(p->ws + p->L.tau) + c0;
+  a.status = reinterpret_cast<uint32_t*>(p->ws + p->L.status) + c0;
+  a.tile_obs = reinterpret_cast<const uint8_t*>(p->ws + p->L.tobs) + static_cast<size_t>(c0) * p->sh.ztiles;
+  a.chain0 = p->desc.chain_id + c0;
   a.advance = 0;
   a.staging_chain = 0;
+  a.trace = nullptr;
+  a.mom = nullptr;
   return a;
 }
 
@@ -1098,12 +1119,13 @@ mf_status check_launch(const char* what) {
   return MF_OK;
 }
 
-// One iteration s' = C (cs alpha s + cb beta) on `spec`.  Forward (adj =
-// false): t^ goes to aux when aux is set.  Adjoint (adj = true): the per-bin
-// sums of Re(conj(t^) aux) are added to gacc, and s is added to acc when set.
+// One iteration s' = C (cs alpha s + cb beta) of every chain on `spec`.
+// Forward (adj = false): t^ goes to aux when aux is set.  Adjoint (adj =
+// true): the per-bin sums of Re(conj(t^) aux) are added to gacc, and s is
+// added to acc when set.
 template <typename R>
-mf_status wiener_iter(mf_problem* p, mf::SweepArgs<R> a, mf::cx<R>* spec, mf::cx<R>* aux, bool adj,
-                      R cs, R cb, R* acc, hipStream_t st) {
+mf_status wiener_iter(mf_problem* p, mf::SweepArgs<R> a, int nc, mf::cx<R>* spec, mf::cx<R>* aux,
+                      bool adj, R cs, R cb, R* acc, hipStream_t st) {
   a.spec = spec;
   a.aux = aux;
   a.acc = acc;
@@ -1112,7 +1134,7 @@ mf_status wiener_iter(mf_problem* p, mf::SweepArgs<R> a, mf::cx<R>* spec, mf::cx
   a.pk_mode = adj ? mf::kPkGrad : mf::kPkNone;
   const int ids[4] = {kZDetK, kYF, adj ? kXAdjK : kXDetK, kYI};
   for (int id : ids) {
-    launch<R>(id, a, p->desc.n, 1, st);
+    launch<R>(id, a, p->desc.n, nc, st);
     const mf_status r = check_launch("Wiener iteration");
     if (r != MF_OK) return r;
   }
@@ -1120,99 +1142,131 @@ mf_status wiener_iter(mf_problem* p, mf::SweepArgs<R> a, mf::cx<R>* spec, mf::cx
 }
 
 template <typename R>
-mf_status wiener_forward(mf_problem* p, int chain, const double* d, const double* pk, int n_iter,
+mf_status wiener_forward(mf_problem* p, int c0, const double* d, const double* pk, int n_iter,
                          int every, char* g, const WLayout& W, double* chi2, double* s_out,
                          hipStream_t st) {
-  const int n = p->desc.n, nb = p->desc.n_bins;
+  const int n = p->desc.n, nb = p->desc.n_bins, nc = W.nc;
   const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
-  const double vcell = std::pow(p->desc.box / n, 3), tau = p->tau[chain];
-  auto a = wiener_args<R>(p, chain, g, W);
-  const R* coef = reinterpret_cast<const R*>(p->ws + p->L.coef) + static_cast<size_t>(chain) * 2 * m;
-  with_n(n, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    hipLaunchKernelGGL((mf::wiener_coef_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
-                       st, coef, reinterpret_cast<R*>(g + W.wcoef), d, entries);
-  });
-  hipLaunchKernelGGL((mf::wiener_table_kernel<R>), dim3((nb + 63) / 64), dim3(64), 0, st, pk,
-                     reinterpret_cast<double*>(g + W.pkg), reinterpret_cast<R*>(g + W.table), tau,
-                     vcell, static_cast<double>(m), nb);
+  const double vcell = std::pow(p->desc.box / n, 3);
+  auto a = wiener_args<R>(p, c0, g, W);
+  const size_t specs = static_cast<size_t>(nc) * W.spec_bytes;
+  for (int c = 0; c < nc; ++c) {
+    const R* coef = reinterpret_cast<const R*>(p->ws + p->L.coef) + static_cast<size_t>(c0 + c) * 2 * m;
+    R* wcoef = reinterpret_cast<R*>(g + W.wcoef) + static_cast<size_t>(c) * 2 * m;
+    with_n(n, [&](auto nn) {
+      constexpr int N = decltype(nn)::value;
+      hipLaunchKernelGGL((mf::wiener_coef_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
+                         st, coef, wcoef, d + c * m, entries);
+    });
+    hipLaunchKernelGGL((mf::wiener_table_kernel<R>), dim3((nb + 63) / 64), dim3(64), 0, st,
+                       pk + c * nb, reinterpret_cast<double*>(g + W.pkg) + c * nb,
+                       reinterpret_cast<R*>(g + W.table) + c * 2 * nb, p->tau[c0 + c], vcell,
+                       static_cast<double>(m), nb);
+  }
   hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st,
-                     reinterpret_cast<R*>(g + W.fwd), W.spec_bytes / sizeof(R));
+                     reinterpret_cast<R*>(g + W.fwd), specs / sizeof(R));
   mf_status r = check_launch("Wiener set-up");
   if (r != MF_OK) return r;
   auto* fwd = reinterpret_cast<mf::cx<R>*>(g + W.fwd);
   for (int k = 0; k < n_iter; ++k) {
     if (k % every == 0)
-      MF_HIP(hipMemcpyAsync(g + W.ckpt + static_cast<size_t>(k / every) * W.spec_bytes, fwd,
-                            W.spec_bytes, hipMemcpyDeviceToDevice, st));
-    if ((r = wiener_iter<R>(p, a, fwd, nullptr, false, R(1), R(1), nullptr, st)) != MF_OK) return r;
+      MF_HIP(hipMemcpyAsync(g + W.ckpt + static_cast<size_t>(k / every) * specs, fwd, specs,
+                            hipMemcpyDeviceToDevice, st));
+    if ((r = wiener_iter<R>(p, a, nc, fwd, nullptr, false, R(1), R(1), nullptr, st)) != MF_OK)
+      return r;
   }
-  a.spec = fwd;
-  launch<R>(kZGet, a, n, 1, st);
   const R* s = reinterpret_cast<const R*>(p->ws + p->L.staging);
-  with_n(n, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    hipLaunchKernelGGL((mf::wiener_chi2_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0, st,
-                       reinterpret_cast<const R*>(g + W.wcoef), d, s, tau,
-                       reinterpret_cast<double*>(g + W.partial), s_out, entries);
-  });
-  hipLaunchKernelGGL(mf::sum_partials_kernel, dim3(1), dim3(mf::kWienerThreads), 0, st,
-                     reinterpret_cast<const double*>(g + W.partial), W.nblk, chi2);
+  for (int c = 0; c < nc; ++c) {   // s_K of chain c through the state staging buffer
+    auto ag = a;
+    ag.spec = fwd;
+    ag.staging_chain = c;
+    launch<R>(kZGet, ag, n, 1, st);
+    with_n(n, [&](auto nn) {
+      constexpr int N = decltype(nn)::value;
+      hipLaunchKernelGGL((mf::wiener_chi2_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
+                         st, reinterpret_cast<const R*>(g + W.wcoef) + c * 2 * m, d + c * m, s,
+                         p->tau[c0 + c], reinterpret_cast<double*>(g + W.partial) + c * W.nblk,
+                         s_out ? s_out + c * m : nullptr, entries);
+    });
+    hipLaunchKernelGGL(mf::sum_partials_kernel, dim3(1), dim3(mf::kWienerThreads), 0, st,
+                       reinterpret_cast<const double*>(g + W.partial) + c * W.nblk, W.nblk, chi2 + c);
+  }
   return check_launch("Wiener chi2");
 }
 
 template <typename R>
-mf_status wiener_backward(mf_problem* p, int chain, const double* d, char* g, const WLayout& W,
+mf_status wiener_backward(mf_problem* p, int c0, const double* d, char* g, const WLayout& W,
                           double* grad_d, double* grad_pk, hipStream_t st) {
-  const int n = p->desc.n, nb = p->desc.n_bins;
+  const int n = p->desc.n, nb = p->desc.n_bins, nc = W.nc;
   const int n_iter = p->wiener.n_iter, every = p->wiener.every;
   const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
-  const double vcell = std::pow(p->desc.box / n, 3), tau = p->tau[chain];
-  auto a = wiener_args<R>(p, chain, g, W);
+  const double vcell = std::pow(p->desc.box / n, 3);
+  auto a = wiener_args<R>(p, c0, g, W);
+  const size_t specs = static_cast<size_t>(nc) * W.spec_bytes;
   auto* fwd = reinterpret_cast<mf::cx<R>*>(g + W.fwd);
   auto* adj = reinterpret_cast<mf::cx<R>*>(g + W.adj);
   R* acc = reinterpret_cast<R*>(g + W.acc);
-  auto slot = [&](int j) { return reinterpret_cast<mf::cx<R>*>(g + W.aux + static_cast<size_t>(j) * W.spec_bytes); };
+  auto slot = [&](int j) { return reinterpret_cast<mf::cx<R>*>(g + W.aux + static_cast<size_t>(j) * specs); };
+  const R* s = reinterpret_cast<const R*>(p->ws + p->L.staging);
   hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1), dim3(256), 0, st,
-                     reinterpret_cast<double*>(g + W.gacc), static_cast<size_t>(nb));
-  hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st, acc, m);
+                     reinterpret_cast<double*>(g + W.gacc), static_cast<size_t>(nc) * nb);
+  hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st, acc, nc * m);
   hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st,
-                     reinterpret_cast<R*>(adj), W.spec_bytes / sizeof(R));
+                     reinterpret_cast<R*>(adj), specs / sizeof(R));
   mf_status r = check_launch("Wiener adjoint set-up");
   if (r != MF_OK) return r;
-  const R neg_inv_tau = static_cast<R>(-1.0 / tau);
   for (int sg = W.n_ckpt - 1; sg >= 0; --sg) {
     const int k0 = sg * every, k1 = std::min(n_iter, k0 + every);
-    MF_HIP(hipMemcpyAsync(fwd, g + W.ckpt + static_cast<size_t>(sg) * W.spec_bytes, W.spec_bytes,
+    MF_HIP(hipMemcpyAsync(fwd, g + W.ckpt + static_cast<size_t>(sg) * specs, specs,
                           hipMemcpyDeviceToDevice, st));
     for (int k = k0; k < k1; ++k)
-      if ((r = wiener_iter<R>(p, a, fwd, slot(k - k0), false, R(1), R(1), nullptr, st)) != MF_OK)
+      if ((r = wiener_iter<R>(p, a, nc, fwd, slot(k - k0), false, R(1), R(1), nullptr, st)) != MF_OK)
         return r;
-    if (sg == W.n_ckpt - 1) {   // fwd now holds s_K
-      a.spec = fwd;
-      launch<R>(kZGet, a, n, 1, st);
+    if (sg == W.n_ckpt - 1) {   // fwd holds s_K: the direct term w (2 d - s_K) of d chi2 / d d
+      for (int c = 0; c < nc; ++c) {
+        auto ag = a;
+        ag.spec = fwd;
+        ag.staging_chain = c;
+        launch<R>(kZGet, ag, n, 1, st);
+        with_n(n, [&](auto nn) {
+          constexpr int N = decltype(nn)::value;
+          hipLaunchKernelGGL((mf::wiener_grad_direct_kernel<R, N>), dim3(W.nblk),
+                             dim3(mf::kWienerThreads), 0, st,
+                             reinterpret_cast<const R*>(g + W.wcoef) + c * 2 * m, d + c * m, s,
+                             p->tau[c0 + c], grad_d + c * m, entries);
+        });
+      }
     }
     for (int k = k1 - 1; k >= k0; --k) {
-      // step k maps g_{k+1} to r_k = C g_{k+1}: g_K = -w d = -beta / tau, and
-      // g_{k+1} = alpha r_{k+1} otherwise (r_{k+1} then joins the sum)
-      r = (k == n_iter - 1)
-              ? wiener_iter<R>(p, a, adj, slot(k - k0), true, R(0), neg_inv_tau, nullptr, st)
-              : wiener_iter<R>(p, a, adj, slot(k - k0), true, R(1), R(0), acc, st);
+      // step k maps g_{k+1} to r_k = C g_{k+1}: g_K = -w d = -beta / tau (of
+      // each chain), and g_{k+1} = alpha r_{k+1} otherwise (r_{k+1} then
+      // joins the sum)
+      if (k == n_iter - 1) {
+        auto af = a;
+        af.cb_over_tau = 1;
+        r = wiener_iter<R>(p, af, nc, adj, slot(k - k0), true, R(0), R(-1), nullptr, st);
+      } else {
+        r = wiener_iter<R>(p, a, nc, adj, slot(k - k0), true, R(1), R(0), acc, st);
+      }
       if (r != MF_OK) return r;
     }
   }
   a.spec = adj;
   a.acc = acc;
-  launch<R>(kZAccK, a, n, 1, st);   // adds r_0
-  const R* s = reinterpret_cast<const R*>(p->ws + p->L.staging);
-  with_n(n, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    hipLaunchKernelGGL((mf::wiener_grad_d_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
-                       st, reinterpret_cast<const R*>(g + W.wcoef), d, s, acc, tau, grad_d, entries);
-  });
-  hipLaunchKernelGGL(mf::wiener_grad_pk_kernel, dim3((nb + 63) / 64), dim3(64), 0, st,
-                     reinterpret_cast<const double*>(g + W.gacc),
-                     reinterpret_cast<const double*>(g + W.pkg), tau, vcell, nb, grad_pk);
+  launch<R>(kZAccK, a, n, nc, st);   // adds r_0
+  for (int c = 0; c < nc; ++c) {
+    with_n(n, [&](auto nn) {
+      constexpr int N = decltype(nn)::value;
+      hipLaunchKernelGGL((mf::wiener_grad_adjoint_kernel<R, N>), dim3(W.nblk),
+                         dim3(mf::kWienerThreads), 0, st,
+                         reinterpret_cast<const R*>(g + W.wcoef) + c * 2 * m, acc + c * m,
+                         grad_d + c * m, entries);
+    });
+    hipLaunchKernelGGL(mf::wiener_grad_pk_kernel, dim3((nb + 63) / 64), dim3(64), 0, st,
+                       reinterpret_cast<const double*>(g + W.gacc) + c * nb,
+                       reinterpret_cast<const double*>(g + W.pkg) + c * nb, p->tau[c0 + c], vcell,
+                       nb, grad_pk + c * nb);
+  }
   return check_launch("Wiener gradient");
 }
 
@@ -1220,12 +1274,15 @@ mf_status wiener_backward(mf_problem* p, int chain, const double* d, char* g, co
 
 extern "C" {
 
-mf_status mf_wiener_workspace_bytes(const mf_problem* p, int32_t n_iter, int32_t ckpt_every,
-                                    size_t* bytes) {
+mf_status mf_wiener_workspace_bytes(const mf_problem* p, int32_t chain, int32_t n_iter,
+                                    int32_t ckpt_every, size_t* bytes) {
   if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
   if (n_iter < 1 || ckpt_every < 1 || ckpt_every > n_iter)
     return fail(MF_E_INVALID_ARG, "need n_iter >= 1 and 1 <= ckpt_every <= n_iter");
-  *bytes = wiener_layout(p, n_iter, ckpt_every).total;
+  int c0 = 0, nc = 0;
+  const mf_status r = wiener_chains(p, chain, &c0, &nc);
+  if (r != MF_OK) return r;
+  *bytes = wiener_layout(p, n_iter, ckpt_every, nc).total;
   return MF_OK;
 }
 
@@ -1233,14 +1290,15 @@ mf_status mf_wiener_forward(mf_problem* p, int32_t chain, const double* d, const
                             int32_t n_iter, int32_t ckpt_every, void* workspace, size_t ws_bytes,
                             double* chi2, double* s_out, void* stream) {
   WLayout W{};
-  mf_status r = check_wiener(p, chain, n_iter, ckpt_every, workspace, ws_bytes, &W);
+  int c0 = 0;
+  mf_status r = check_wiener(p, chain, n_iter, ckpt_every, workspace, ws_bytes, &W, &c0);
   if (r != MF_OK) return r;
   if (!d || !pk || !chi2) return fail(MF_E_INVALID_ARG, "d, pk and chi2 must be device pointers");
   p->wiener = WienerRun{};
   hipStream_t hs = static_cast<hipStream_t>(stream);
   char* g = static_cast<char*>(workspace);
-  r = p->fp64() ? wiener_forward<double>(p, chain, d, pk, n_iter, ckpt_every, g, W, chi2, s_out, hs)
-                : wiener_forward<float>(p, chain, d, pk, n_iter, ckpt_every, g, W, chi2, s_out, hs);
+  r = p->fp64() ? wiener_forward<double>(p, c0, d, pk, n_iter, ckpt_every, g, W, chi2, s_out, hs)
+                : wiener_forward<float>(p, c0, d, pk, n_iter, ckpt_every, g, W, chi2, s_out, hs);
   if (r == MF_OK) p->wiener = WienerRun{workspace, chain, n_iter, ckpt_every};
   return r;
 }
@@ -1251,13 +1309,14 @@ mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void
   if (p->wiener.gws == nullptr || p->wiener.gws != workspace || p->wiener.chain != chain)
     return fail(MF_E_STATE, "no Wiener forward run of chain %d with this workspace", chain);
   WLayout W{};
-  mf_status r = check_wiener(p, chain, p->wiener.n_iter, p->wiener.every, workspace, ws_bytes, &W);
+  int c0 = 0;
+  mf_status r = check_wiener(p, chain, p->wiener.n_iter, p->wiener.every, workspace, ws_bytes, &W, &c0);
   if (r != MF_OK) return r;
   if (!d || !grad_d || !grad_pk) return fail(MF_E_INVALID_ARG, "d, grad_d and grad_pk must be device pointers");
   hipStream_t hs = static_cast<hipStream_t>(stream);
   char* g = static_cast<char*>(workspace);
-  return p->fp64() ? wiener_backward<double>(p, chain, d, g, W, grad_d, grad_pk, hs)
-                   : wiener_backward<float>(p, chain, d, g, W, grad_d, grad_pk, hs);
+  return p->fp64() ? wiener_backward<double>(p, c0, d, g, W, grad_d, grad_pk, hs)
+                   : wiener_backward<float>(p, c0, d, g, W, grad_d, grad_pk, hs);
 }
 
 }  // extern "C"

@@ -58,6 +58,7 @@ struct SweepArgs {
   uint32_t key0, key1;
   // Deterministic messenger iteration (the Wiener filter) and its adjoint:
   R cs, cb;               // z-pass forms t = cs alpha s + cb beta (no draw)
+  int32_t cb_over_tau;    // nonzero: cb / tau of the chain replaces cb
   R* acc;                 // z-pass order [entry][2]: adds s before the messenger step
   cx<R>* aux;             // x-pass layout: t^ of one iteration (stored or read)
   double* gacc;           // [chain][nb] accumulated d chi2 / d f_b
@@ -324,12 +325,13 @@ zpass_kernel(SweepArgs<R> a) {
     const int tile = blockIdx.y * (N / T::P) + blk;
     const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m + static_cast<size_t>(tile) * EPT * NT * 4;
     const bool obs = tile_observed(a, c, tile);
+    const R cb = a.cb_over_tau ? static_cast<R>(static_cast<double>(a.cb) / a.tau[c]) : a.cb;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       R cf[4] = {R(1), R(1), R(0), R(0)};
       if (obs) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
       const cx<R> s = v[e];
-      v[e] = cx<R>{a.cs * cf[0] * s.x + a.cb * cf[2], a.cs * cf[1] * s.y + a.cb * cf[3]};
+      v[e] = cx<R>{a.cs * cf[0] * s.x + cb * cf[2], a.cs * cf[1] * s.y + cb * cf[3]};
     }
   } else {
     const R tau = static_cast<R>(a.tau[c]);

@@ -122,19 +122,31 @@ sum_partials_kernel(const double* partial, int n, double* out) {
 }
 
 // d chi2 / d d_i = w_i (2 d_i - s_K,i) + (1 - alpha_i) sum_k r_k,i, where r_k
-// is the adjoint field (acc, z-pass order); zero on unobserved voxels.
+// is the adjoint field; zero on unobserved voxels.  The direct term is
+// written once s_K is known, the adjoint sum (acc, z-pass order) added last.
 template <typename R, int N>
 __global__ void __launch_bounds__(kWienerThreads)
-wiener_grad_d_kernel(const R* wcoef, const double* d, const R* s, const R* acc, double tau,
-                     double* grad_d, size_t entries) {
+wiener_grad_direct_kernel(const R* wcoef, const double* d, const R* s, double tau, double* grad_d,
+                          size_t entries) {
   const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
   if (idx >= entries) return;
   size_t va = 0, vb = 0;
   entry_voxels<R, N>(idx, va, vb);
   const double oa = 1.0 - static_cast<double>(wcoef[idx * 4]);
   const double ob = 1.0 - static_cast<double>(wcoef[idx * 4 + 1]);
-  grad_d[va] = oa / tau * (2.0 * d[va] - s[va]) + oa * static_cast<double>(acc[idx * 2]);
-  grad_d[vb] = ob / tau * (2.0 * d[vb] - s[vb]) + ob * static_cast<double>(acc[idx * 2 + 1]);
+  grad_d[va] = oa / tau * (2.0 * d[va] - s[va]);
+  grad_d[vb] = ob / tau * (2.0 * d[vb] - s[vb]);
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kWienerThreads)
+wiener_grad_adjoint_kernel(const R* wcoef, const R* acc, double* grad_d, size_t entries) {
+  const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
+  if (idx >= entries) return;
+  size_t va = 0, vb = 0;
+  entry_voxels<R, N>(idx, va, vb);
+  grad_d[va] += (1.0 - static_cast<double>(wcoef[idx * 4])) * static_cast<double>(acc[idx * 2]);
+  grad_d[vb] += (1.0 - static_cast<double>(wcoef[idx * 4 + 1])) * static_cast<double>(acc[idx * 2 + 1]);
 }
 
 // d chi2 / d P_b (physical units) = d chi2 / d f_b * tau / (P_b + tau)^2 / V_cell.

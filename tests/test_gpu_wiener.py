@@ -156,6 +156,39 @@ def test_unsupported_size_is_rejected():
     assert e.value.status == binding.MF_E_UNSUPPORTED_SIZE
 
 
+def test_all_chains_in_one_launch_match_single_chain_runs_and_oracle():
+    import torch
+    k, every = 7, 3
+    ws, pbs = [], []
+    for c in range(3):
+        w = workloads.small_workload(32, 8, mask="random", precision="fp64", seed=120 + c,
+                                     rng_seed=31, mask_frac=0.1 + 0.1 * c, sigma2=0.5 + c)
+        ws.append(w)
+        pbs.append(workloads.make_problem(w))
+    smp = binding.Sampler([pb["data"] for pb in pbs], [pb["noise_var"] for pb in pbs],
+                          [pb["pk_init"] for pb in pbs], 8, ws[0].box, seed=31, precision="fp64",
+                          sample_pk=False)
+    pk = np.stack([(0.4 + 0.2 * c) * workloads.power_spectrum(workloads.bin_centres(ws[c]), ws[c])
+                   for c in range(3)])
+    d = torch.from_numpy(np.stack([pb["data"] for pb in pbs])).cuda()
+    pk_t = torch.from_numpy(pk).cuda()
+    wf = binding.WienerFilter(smp, k, every, chain=None)
+    chi2, _ = wf.forward(d, pk_t)
+    gd, gp = wf.backward(d)
+    for c in range(3):
+        one = binding.WienerFilter(smp, k, every, chain=c)
+        c1, _ = one.forward(d[c].contiguous(), pk_t[c].contiguous())
+        gd1, gp1 = one.backward(d[c].contiguous())
+        assert float(c1) == float(chi2[c])
+        assert torch.equal(gd1, gd[c]) and torch.equal(gp1, gp[c])
+        prob = oracle_problem(ws[c], pbs[c])
+        loss, gp_ref, gd_ref = adjoint.wf_gradient(prob, pk[c] / ws[c].cell_volume, k)
+        e = max(abs(float(chi2[c]) - loss) / abs(loss), _rel(gd[c].cpu().numpy(), gd_ref),
+                _rel(gp[c].cpu().numpy(), gp_ref / ws[c].cell_volume))
+        print(f"  chain {c}: err {e:.2e}", flush=True)
+        assert e < TOL["fp64"]
+
+
 def test_full_size_128_survey_50_iterations():
     """The 128^3 survey problem, 32 bins, 50 iterations, checkpoint every 10
     (FP32) against the FP64 oracle."""
