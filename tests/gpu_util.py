@@ -15,8 +15,9 @@ def oracle_problem(w, pb, chain=0, tau=None):
                                 chain=chain, tau=tau)
 
 
-def run_oracle(w, pb, n_sweeps, sample_pk=True, s0=None, p0=None, first_sweep=0, chain=0):
-    prob = oracle_problem(w, pb, chain=chain)
+def run_oracle(w, pb, n_sweeps, sample_pk=True, s0=None, p0=None, first_sweep=0, chain=0,
+               tau=None):
+    prob = oracle_problem(w, pb, chain=chain, tau=tau)
     st = sampler.State(s=np.zeros((w.n,) * 3) if s0 is None else np.array(s0, dtype=np.float64),
                        p_grid=(pb["pk_init"] if p0 is None else p0) / w.cell_volume,
                        sweep=first_sweep)

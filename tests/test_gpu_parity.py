@@ -122,3 +122,31 @@ def test_parity_mixed_radix_sizes(n, precision):
     96 = 6 * 16): random masks with 10-40% unobserved voxels."""
     err_s, err_p = _case(n, 16, precision, "random", 10, seed=n, mask_frac=0.1 + 0.3 * (n % 7) / 7)
     assert err_s < TOL[precision] and err_p < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_bin(precision):
+    w = workloads.small_workload(32, 1, mask="random", precision=precision, seed=131, rng_seed=132)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    smp.sweep(5)
+    s_gpu, p_gpu, _ = smp.state()
+    s_ref, p_ref = run_oracle(w, pb, 5)
+    err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+    print(f"single bin {precision}: err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
+    assert err_s < TOL[precision] and err_p < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_user_tau_below_the_smallest_noise(precision):
+    w = workloads.small_workload(32, 8, mask="random", precision=precision, seed=133, rng_seed=134)
+    pb = workloads.make_problem(w)
+    tau = 0.3 * float(np.min(pb["noise_var"][np.isfinite(pb["noise_var"])]))
+    smp = gpu_sampler(w, pb, tau=tau)
+    assert smp.tau() == pytest.approx(tau, rel=1e-15)
+    smp.sweep(5)
+    s_gpu, p_gpu, _ = smp.state()
+    s_ref, p_ref = run_oracle(w, pb, 5, tau=tau)
+    err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+    print(f"user tau {precision}: err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
+    assert err_s < TOL[precision] and err_p < TOL[precision]
