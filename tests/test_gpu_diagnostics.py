@@ -107,3 +107,31 @@ def test_diagnostic_errors():
     assert e.value.status == binding.MF_E_STATE
     with pytest.raises(binding.MFError):
         smp.set_diagnostics(start=0, thin=0, trace_cap=2)
+
+
+def test_gpu_fixed_power_moments_match_the_dense_posterior():
+    """End-to-end statistics on the GPU: 8 chains at fixed P on an 8^3 grid,
+    Welford moments over 20,000 sweeps each, against the dense Cholesky
+    posterior mean and variance (the Wiener posterior the sampler targets)."""
+    from oracle import wiener
+    w = workloads.small_workload(8, 4, mask="random", precision="fp64", seed=141, rng_seed=142,
+                                 mask_frac=0.3)
+    pb = workloads.make_problem(w)
+    p_grid = workloads.power_spectrum(workloads.bin_centres(w), w) / w.cell_volume
+    chains = 8
+    smp = binding.Sampler([pb["data"]] * chains, [pb["noise_var"]] * chains,
+                          [p_grid * w.cell_volume] * chains, w.n_bins, w.box, seed=143,
+                          precision="fp64", sample_pk=False)
+    smp.set_diagnostics(start=200, thin=1, moments=True)
+    smp.sweep(20_200)
+    means = np.stack([smp.moments(c)[0].cpu().numpy().ravel() for c in range(chains)])
+    vars_ = np.stack([smp.moments(c)[1].cpu().numpy().ravel() for c in range(chains)])
+    mean_ref, cov_ref = wiener.posterior(8, w.n_bins, p_grid, pb["data"], pb["noise_var"])
+    var_ref = np.diag(cov_ref)
+    se = means.std(axis=0, ddof=1) / np.sqrt(chains)
+    z = (means.mean(axis=0) - mean_ref) / se
+    ratio = vars_.mean(axis=0) / var_ref
+    print(f"posterior moments: mean z^2 {np.mean(z ** 2):.3f} (t_7: 1.4), "
+          f"variance ratio {ratio.mean():.4f} +- {ratio.std():.4f}", flush=True)
+    assert abs(np.mean(z)) < 0.3 and 0.7 < np.mean(z ** 2) < 2.3
+    assert abs(ratio.mean() - 1.0) < 0.02
