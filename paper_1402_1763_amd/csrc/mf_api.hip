@@ -1,7 +1,11 @@
 // C ABI of the messenger-field Gibbs sampler (declarations and contract in
-// include/mf.h).  Host side: descriptor validation, workspace layout, FP64
-// set-up of the per-voxel messenger coefficients, tau, bin thresholds, mode
-// counts and twiddles, and the launch sequence of a sweep.
+// include/mf.h).  Host side:
+//  - descriptor validation and the workspace layout;
+//  - FP64 set-up of the per-voxel messenger coefficients, tau, bin
+//    thresholds, mode counts and twiddles;
+//  - the launch sequences of the Gibbs and mixing sweeps and of the Wiener
+//    iteration and its adjoint;
+//  - state, checkpoints, graphs, diagnostics and the x-transform autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

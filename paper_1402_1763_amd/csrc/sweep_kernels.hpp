@@ -6,20 +6,25 @@
 //   table        [b][2]        R      per-bin (A_b, B_b) of the signal draw
 //   pk           [b]           double P_b in grid units (variance per voxel)
 //   partials     [b][wg]       double per-workgroup shell sums of the x-pass
+//                                     (a second set for the mixing sweep)
 // Between sweeps `spec` holds s transformed along z only, Y = DFT_z(s) / N
 // (a real-to-half-complex DFT of each z pencil), so keeping the state costs
 // no extra pass.
 //
-// One sweep = four launches:
+// One Gibbs sweep = four launches:
 //   z-pass  : inverse z-DFT (-> s), messenger draw t, forward z-DFT of t
-//   y-pass  : forward y-DFT (and, for 32 <= N <= 256, the first half of the
-//             forward x-DFT, see "x split")
+//   y-pass  : forward y-DFT (and, on the split path, 32 <= N <= 256, the
+//             first half of the forward x-DFT, see "x split")
 //   x-pass  : forward x-DFT (-> t^), signal draw s^, shell sums, inverse x-DFT
 //   y-pass  : inverse y-DFT (and the last half of the inverse x-DFT), plus the
 //             per-bin reduction of the shell sums and the inverse-gamma draw of
 //             P(k) in extra workgroups
 // The signal draw folds the inverse transform's 1/M into s^, so the stored
-// field is s^/M and every DFT is unnormalised.
+// field is s^/M and every DFT is unnormalised.  The same kernels serve the
+// mixing sweep (kXMix, then mix_pk_kernel and xmixinv_kernel between the
+// x-pass and the inverse y-pass), the deterministic Wiener iteration and its
+// adjoint (kZDet / kZAccum, kXDet / kXAdj, kPkGrad), and the diagnostics
+// (Welford moments in the z-pass, P traces in the P workgroups).
 #pragma once
 
 #include <hip/hip_runtime.h>
