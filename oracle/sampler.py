@@ -5,9 +5,11 @@ Model (paper Sec. "The augmented Wiener posterior"): data d = R s + eps with
 diagonal noise covariance N, Gaussian signal prior with covariance S that is
 diagonal in Fourier space, and a messenger field t with covariance T = tau 1.
 Marginalising t recovers the Wiener posterior when the augmented noise is
-N~ = N - R^T T R, which requires 0 < tau <= N_i on every observed voxel; tau
-is taken as the smallest observed N_i.  Here R_i = 1 on observed voxels and
-R_i = 0 (equivalently N_i = +inf) on unobserved ones.
+N~ = N - R^T T R, which requires 0 < tau <= [(R^-1)^T N R^-1]_i = N_i / R_i^2
+on every observed voxel; tau is taken as the smallest observed N_i / R_i^2.
+R is diagonal: a per-voxel response R_i, 1 unless given.  A voxel is
+observed when R_i != 0 and N_i is finite; elsewhere the paper's R^2 = 0
+branch applies (N_i = +inf is the same thing).
 
 One sweep of chain c, sweep index n (paper Algs. 1 and 2, eqs. for mu^t,
 sigma^t, mu^s, sigma^s and the inverse-gamma conditional):
@@ -67,6 +69,7 @@ class Problem:
     tau: float
     seed: int
     chain: int = 0
+    response: Optional[np.ndarray] = None   # (n, n, n) float64 R_i; None: R_i = 1
 
     @property
     def m(self) -> int:
@@ -78,26 +81,39 @@ class Problem:
 
     @property
     def observed(self) -> np.ndarray:
-        return np.isfinite(self.noise_var)
+        if self.response is None:
+            return np.isfinite(self.noise_var)
+        return np.isfinite(self.noise_var) & (self.response != 0.0)
+
+    @property
+    def r(self) -> np.ndarray:
+        """R_i on observed voxels, 0 elsewhere."""
+        one = np.ones_like(self.noise_var) if self.response is None else self.response
+        return np.where(self.observed, one, 0.0)
 
 
 def make_problem(data, noise_var, n_bins: int, box: float, seed: int, chain: int = 0,
-                 tau: Optional[float] = None) -> Problem:
-    """tau defaults to the smallest observed noise variance; a given tau must not
-    exceed it (the augmented noise must stay positive)."""
+                 tau: Optional[float] = None, response=None) -> Problem:
+    """tau defaults to the smallest observed N_i / R_i^2; a given tau must not
+    exceed it (the augmented noise N - R T R must stay positive)."""
     data = np.asarray(data, dtype=np.float64)
     noise_var = np.asarray(noise_var, dtype=np.float64)
+    if response is not None:
+        response = np.asarray(response, dtype=np.float64)
+        if not np.all(np.isfinite(response)):
+            raise ValueError("response not finite")
     n = data.shape[0]
-    obs = np.isfinite(noise_var)
+    prob = Problem(n=n, box=float(box), n_bins=int(n_bins), data=data, noise_var=noise_var,
+                   tau=0.0, seed=int(seed), chain=int(chain), response=response)
+    obs = prob.observed
     if not obs.any():
         raise ValueError("no observed voxel")
-    tau_max = float(noise_var[obs].min())
+    tau_max = float(np.min(noise_var[obs] / prob.r[obs] ** 2))
     if tau is None or tau <= 0:
         tau = tau_max
     elif tau > tau_max:
-        raise ValueError("tau exceeds the smallest observed noise variance")
-    return Problem(n=n, box=float(box), n_bins=int(n_bins), data=data,
-                   noise_var=noise_var, tau=float(tau), seed=int(seed), chain=int(chain))
+        raise ValueError("tau exceeds the smallest observed N_i / R_i^2")
+    return dataclasses.replace(prob, tau=float(tau))
 
 
 # ---------------------------------------------------------------- draws
@@ -130,9 +146,9 @@ def signal_normals(n: int, seed: int, chain: int, sweep: int):
 
 # ---------------------------------------------------------------- steps
 def messenger_moments(s: np.ndarray, prob: Problem):
-    """Conditional mean and variance of t given s, d (R in {0, 1}, T = tau)."""
+    """Conditional mean and variance of t given s, d (T = tau)."""
     T = prob.tau
-    R = prob.observed.astype(np.float64)
+    R = prob.r
     n_tilde = np.where(prob.observed, prob.noise_var - T * R * R, 1.0)
     den = T * R * R + n_tilde
     d = np.where(prob.observed, prob.data, 0.0)

@@ -2,8 +2,9 @@
 
 For fixed P the target of the sampler is the Wiener posterior (paper Eq.
 target_wiener_post): Gaussian with mean m = S R^T (R S R^T + N)^-1 d and
-covariance C = S - S R^T (R S R^T + N)^-1 R S, where R selects the observed
-voxels.  S is circulant on the periodic grid, S_xy = c(x - y) with
+covariance C = S - S R^T (R S R^T + N)^-1 R S, with R diagonal (the per-voxel
+response; 1 unless given) restricted to the observed voxels (finite N,
+R != 0).  S is circulant on the periodic grid, S_xy = c(x - y) with
 c = inverse DFT (with 1/M) of the per-voxel power P_grid(k), P(0) = 0.
 
 This builds the M x M matrices explicitly and factorises them by Cholesky, so
@@ -36,17 +37,18 @@ def signal_covariance(n: int, power_full: np.ndarray) -> np.ndarray:
     return c[diff[..., 0], diff[..., 1], diff[..., 2]]
 
 
-def posterior(n: int, n_bins: int, p_grid, data, noise_var):
+def posterior(n: int, n_bins: int, p_grid, data, noise_var, response=None):
     """Wiener-filter mean and covariance (both flattened in C order)."""
     s_mat = signal_covariance(n, full_grid_power(n, n_bins, p_grid))
     d = np.asarray(data, dtype=np.float64).ravel()
     nv = np.asarray(noise_var, dtype=np.float64).ravel()
-    o = np.isfinite(nv)
-    a = s_mat[np.ix_(o, o)] + np.diag(nv[o])
+    r = np.ones_like(nv) if response is None else np.asarray(response, dtype=np.float64).ravel()
+    o = np.isfinite(nv) & (r != 0.0)
+    s_xo_r = s_mat[:, o] * r[o][None, :]                     # S R^T, observed columns
+    a = r[o][:, None] * s_xo_r[o, :] + np.diag(nv[o])        # R S R^T + N
     cho = scipy.linalg.cho_factor(a, lower=True)
-    s_xo = s_mat[:, o]
-    mean = s_xo @ scipy.linalg.cho_solve(cho, d[o])
-    cov = s_mat - s_xo @ scipy.linalg.cho_solve(cho, s_xo.T)
+    mean = s_xo_r @ scipy.linalg.cho_solve(cho, d[o])
+    cov = s_mat - s_xo_r @ scipy.linalg.cho_solve(cho, s_xo_r.T)
     return mean, cov
 
 
