@@ -146,10 +146,12 @@ def signal_normals(n: int, seed: int, chain: int, sweep: int):
 
 # ---------------------------------------------------------------- steps
 def messenger_moments(s: np.ndarray, prob: Problem):
-    """Conditional mean and variance of t given s, d (T = tau)."""
+    """Conditional mean and variance of t given s, d (T = tau).  N~ = N - T R^2
+    is >= 0 by the choice of tau and exactly 0 where N / R^2 is smallest;
+    rounding of T R^2 there can leave -1 ulp, which is set back to 0."""
     T = prob.tau
     R = prob.r
-    n_tilde = np.where(prob.observed, prob.noise_var - T * R * R, 1.0)
+    n_tilde = np.where(prob.observed, np.maximum(prob.noise_var - T * R * R, 0.0), 1.0)
     den = T * R * R + n_tilde
     d = np.where(prob.observed, prob.data, 0.0)
     mu = np.where(R * R > 0, T / den * R * d + n_tilde / den * s, s)

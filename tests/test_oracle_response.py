@@ -75,6 +75,26 @@ def test_messenger_step_limits_with_response():
     assert np.allclose(var[o], prob.tau * (1 - wgt), rtol=1e-12, atol=0)
 
 
+def test_augmented_noise_stays_non_negative_at_the_tau_voxel():
+    """With tau = N / R^2 of the minimising voxel, N - tau R^2 is 0 in exact
+    arithmetic but rounds to -1 ulp for this (N, R) pair: the messenger
+    variance there must come out 0, not negative."""
+    n = 8
+    nv = np.full((n,) * 3, 2.0)
+    r = np.ones((n,) * 3)
+    nv[3, 4, 5], r[3, 4, 5] = 0.5002257126660961, 1.6887569038041037
+    tau = nv[3, 4, 5] / r[3, 4, 5] ** 2
+    assert nv[3, 4, 5] - tau * r[3, 4, 5] * r[3, 4, 5] < 0.0   # the rounding case
+    d = np.random.default_rng(1).standard_normal((n,) * 3)
+    prob = sampler.make_problem(d, nv, 4, 500.0, 1, response=r)
+    assert prob.tau == tau
+    mu, var = sampler.messenger_moments(np.zeros((n,) * 3), prob)
+    assert np.all(var >= 0.0) and var[3, 4, 5] == 0.0
+    assert mu[3, 4, 5] == pytest.approx(d[3, 4, 5] / r[3, 4, 5], rel=1e-15)
+    st = sampler.run_chain(prob, sampler.State(s=np.zeros((n,) * 3), p_grid=np.ones(4)), 2)
+    assert np.all(np.isfinite(st.s)) and np.all(np.isfinite(st.p_grid))
+
+
 @pytest.mark.slow
 def test_fixed_power_chain_matches_dense_posterior_with_response():
     n, nbins = 8, 4
