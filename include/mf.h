@@ -74,6 +74,8 @@ typedef struct {
   int32_t precision;  /* mf_precision */
   int32_t sample_pk;  /* 1: Gibbs update of P(k) each sweep; 0: P held fixed */
   int32_t n_chains;   /* independent chains sharing N, bins, box and seed (>= 1) */
+  int32_t has_response; /* 1: mf_init_problem takes a per-voxel response R per
+                           chain; 0: R = 1 on every observed voxel */
 } mf_chain_desc;
 
 typedef struct mf_problem mf_problem;
@@ -91,22 +93,31 @@ int32_t mf_supported_n(int32_t n);
  * Errors: MF_E_INVALID_ARG, MF_E_UNSUPPORTED_SIZE. */
 mf_status mf_workspace_bytes(const mf_chain_desc* desc, size_t* bytes);
 
-/* Set up a problem (model of Sec. 2: data model, messenger covariance tau).
+/* Set up a problem (model of Sec. 2: data model d = R s + eps with diagonal
+ * response R and noise covariance N, messenger covariance tau).
  *  data[c], noise_var[c]: host, M doubles each, chain c's data and noise
  *      variance (+INF = unobserved).  Observed voxels need finite d and N > 0.
+ *  response: NULL when desc->has_response = 0 (R = 1); otherwise a host array
+ *      of n_chains pointers, each M finite doubles R_i.  R_i = 0 marks an
+ *      unobserved voxel (its d and N are then ignored), as N_i = +INF does.
  *  pk_init[c]: host, n_bins doubles, initial P per bin (physical units, >= 0).
  *  s_init: NULL (every chain starts at s = 0) or host array of n_chains
  *      pointers, each M doubles (a NULL entry also means s = 0).
  *  workspace: device pointer of workspace_bytes >= mf_workspace_bytes(desc).
- * Per chain, tau is the smallest observed N_i unless desc->tau > 0, which
- * must not exceed it (MF_E_TAU).  Per-voxel coefficients are formed in FP64
- * on the host and uploaded.  Enqueues on `stream` and synchronises it.
- * Errors: MF_E_INVALID_ARG, MF_E_UNSUPPORTED_SIZE, MF_E_TAU, MF_E_NONFINITE,
+ * Per chain, tau is the smallest observed N_i / R_i^2 (the bound of Sec. 2)
+ * unless desc->tau > 0, which must not exceed it (MF_E_TAU).  The messenger
+ * conditional of Sec. 3.1 is folded into per-voxel coefficients
+ * alpha = 1 - tau R^2 / N and beta = tau R d / N, formed in FP64 on the host
+ * and uploaded; the sweep itself does not depend on R otherwise.  Enqueues on
+ * `stream` and synchronises it.
+ * Errors: MF_E_INVALID_ARG (also a response given or missing against
+ * desc->has_response), MF_E_UNSUPPORTED_SIZE, MF_E_TAU, MF_E_NONFINITE,
  * MF_E_WORKSPACE, MF_E_DEVICE.  On error *out is NULL. */
 mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
-                          const double* const* noise_var, const double* const* pk_init,
-                          const double* const* s_init, void* workspace, size_t workspace_bytes,
-                          void* stream, mf_problem** out);
+                          const double* const* noise_var, const double* const* response,
+                          const double* const* pk_init, const double* const* s_init,
+                          void* workspace, size_t workspace_bytes, void* stream,
+                          mf_problem** out);
 
 /* Enqueue n_sweeps >= 0 Gibbs sweeps of every chain (Algs. 1 and 2 with shell
  * averaging; the P(k) step only when sample_pk = 1).  Asynchronous.
@@ -234,13 +245,16 @@ void mf_graph_destroy(mf_graph* g);
  * With every unit normal of the sweep set to zero and P held fixed, one
  * sweep becomes the iteration s_{k+1} = C (alpha s_k + beta): the means of
  * the messenger and signal conditionals (Sec. 3.1).  Here C = F^-1 diag(f) F
- * with f_b = P_b / (P_b + tau) and f = 0 at k = 0, alpha = 1 - tau / N_i and
- * beta = tau d_i / N_i on observed voxels, and (1, 0) elsewhere.  The
- * iteration converges to the Wiener filter S (S + N)^-1 d.  Starting from
- * s_0 = 0, K iterations give s_K, and the loss is
- *   chi2_K = sum_i d_i (d_i - s_K,i) / N_i   over observed voxels,
- * which tends to d^T (S + N)^-1 d as K grows.  The noise model (N_i, the
- * mask and tau) is the chain's; d and P are inputs of each call.
+ * with f_b = P_b / (P_b + tau) and f = 0 at k = 0, alpha = 1 - tau R_i^2 / N_i
+ * and beta = tau R_i d_i / N_i on observed voxels, and (1, 0) elsewhere.  The
+ * iteration converges to the Wiener filter S R (R S R + N)^-1 d.  Starting
+ * from s_0 = 0, K iterations give s_K, and the loss is
+ *   chi2_K = sum_i d_i (d_i - R_i s_K,i) / N_i   over observed voxels,
+ * which tends to d^T (R S R + N)^-1 d as K grows.  The noise model (N_i, R_i,
+ * the mask and tau) is the chain's; d and P are inputs of each call.  With a
+ * response the library runs the same iteration on d / R with noise N / R^2
+ * (an exact rescaling: s_K and chi2_K are unchanged) and scales the gradient
+ * with respect to d by 1 / R.
  *
  * chain >= 0 selects one chain.  chain = -1 runs every chain of the problem
  * in the same launches (arrays then hold the chains one after another).
@@ -248,10 +262,13 @@ void mf_graph_destroy(mf_graph* g);
  * mf_wiener_workspace_bytes: size of the caller-owned device workspace for
  *   that chain selection, K iterations and a checkpoint every `ckpt_every`.
  *   Per chain it holds ceil(K / E) checkpoints plus E stored spectra, about
- *   (ceil(K/E) + E + 6) * 8 M bytes in FP32 mode.
+ *   (ceil(K/E) + E + 6) * 8 M bytes in FP32 mode, and 8 M bytes more with a
+ *   response.
  * mf_wiener_forward: d (FP64, M per chain, [ix][iy][iz]; ignored where
  *   unobserved) and pk (FP64, n_bins per chain, physical units) are device
- *   arrays.  Writes chi2_K to the device doubles `chi2` (one per chain) and,
+ *   arrays.  d is data in the problem's model d = R s + eps, and
+ *   chi2_K = sum over observed i of d_i (d_i - R_i s_K,i) / N_i.  Writes
+ *   chi2_K to the device doubles `chi2` (one per chain) and,
  *   when `s_out` (device FP64, M per chain) is not NULL, s_K.  Checkpoints of
  *   s_k every `ckpt_every` iterations stay in the workspace for
  *   mf_wiener_backward.  The chains' Gibbs state is not touched.

@@ -46,6 +46,7 @@ class mf_chain_desc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("sample_pk", ctypes.c_int32),
         ("n_chains", ctypes.c_int32),
+        ("has_response", ctypes.c_int32),
     ]
 
 
@@ -54,7 +55,7 @@ SIGNATURES = {
     "mf_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(mf_chain_desc),
                                           ctypes.POINTER(ctypes.c_size_t)]),
     "mf_init_problem": (ctypes.c_int, [ctypes.POINTER(mf_chain_desc), _c_double_pp, _c_double_pp,
-                                       _c_double_pp, _c_double_pp, ctypes.c_void_p,
+                                       _c_double_pp, _c_double_pp, _c_double_pp, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "mf_gibbs_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -152,10 +153,11 @@ def _ptr_array(arrays):
 
 def make_desc(n: int, n_bins: int, box: float, seed: int, precision: str = "fp32",
               tau: float = 0.0, chain_id: int = 0, sample_pk: bool = True,
-              n_chains: int = 1) -> mf_chain_desc:
+              n_chains: int = 1, has_response: bool = False) -> mf_chain_desc:
     prec = {"fp64": MF_PREC_FP64, "fp32": MF_PREC_FP32}[precision]
     return mf_chain_desc(n=n, n_bins=n_bins, box=box, tau=tau, seed=seed, chain_id=chain_id,
-                         precision=prec, sample_pk=1 if sample_pk else 0, n_chains=n_chains)
+                         precision=prec, sample_pk=1 if sample_pk else 0, n_chains=n_chains,
+                         has_response=1 if has_response else 0)
 
 
 def mf_supported_n(n: int) -> bool:
@@ -181,14 +183,16 @@ def _stream_ptr(stream) -> Optional[int]:
 
 def mf_init_problem(desc: mf_chain_desc, data: Sequence, noise_var: Sequence, pk_init: Sequence,
                     s_init: Optional[Sequence], workspace_ptr: int, workspace_bytes: int,
-                    stream=None) -> int:
+                    stream=None, response: Optional[Sequence] = None) -> int:
     data = [_f64(a) for a in data]
     noise_var = [_f64(a) for a in noise_var]
     pk_init = [_f64(a) for a in pk_init]
     s_list = None if s_init is None else [None if a is None else _f64(a) for a in s_init]
+    r_list = None if response is None else [_f64(a) for a in response]
     handle = ctypes.c_void_p()
     _check(load().mf_init_problem(
-        ctypes.byref(desc), _ptr_array(data), _ptr_array(noise_var), _ptr_array(pk_init),
+        ctypes.byref(desc), _ptr_array(data), _ptr_array(noise_var),
+        _ptr_array(r_list) if r_list is not None else None, _ptr_array(pk_init),
         _ptr_array(s_list) if s_list is not None else None, ctypes.c_void_p(workspace_ptr),
         workspace_bytes, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(handle)))
     return handle.value
@@ -330,30 +334,33 @@ class Sampler:
     """A problem on cuda:0 with a torch-owned workspace.
 
     data, noise_var: (N, N, N) float64 arrays (or lists of them, one per
-    chain); noise_var = +inf marks unobserved voxels.  pk_init: initial P per
-    bin in physical units."""
+    chain); noise_var = +inf marks unobserved voxels.  response: None (R = 1)
+    or the per-voxel response R of the data model d = R s + eps, in the same
+    form (R = 0 also marks unobserved voxels).  pk_init: initial P per bin in
+    physical units."""
 
     def __init__(self, data, noise_var, pk_init, n_bins: int, box: float, seed: int,
                  precision: str = "fp32", tau: float = 0.0, chain_id: int = 0,
-                 sample_pk: bool = True, s_init=None, device: str = "cuda"):
+                 sample_pk: bool = True, s_init=None, device: str = "cuda", response=None):
         import torch
         multi = isinstance(data, (list, tuple))
         data_l = list(data) if multi else [data]
         noise_l = list(noise_var) if multi else [noise_var]
         pk_l = list(pk_init) if multi else [pk_init]
         s_l = None if s_init is None else (list(s_init) if multi else [s_init])
+        r_l = None if response is None else (list(response) if multi else [response])
         self.n = int(np.shape(data_l[0])[0])
         self.n_bins = n_bins
         self.n_chains = len(data_l)
         self.desc = make_desc(self.n, n_bins, box, seed, precision, tau, chain_id, sample_pk,
-                              self.n_chains)
+                              self.n_chains, has_response=response is not None)
         self.workspace_bytes = mf_workspace_bytes(self.desc)
         self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self._ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream()
         self.handle = mf_init_problem(self.desc, data_l, noise_l, pk_l, s_l, self._ptr,
-                                      self.workspace_bytes, self.stream.cuda_stream)
+                                      self.workspace_bytes, self.stream.cuda_stream, r_l)
 
     def sweep(self, n_sweeps: int = 1):
         mf_gibbs_sweep(self.handle, n_sweeps, self.stream.cuda_stream)

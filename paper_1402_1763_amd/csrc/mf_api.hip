@@ -87,7 +87,7 @@ Shape shape_of(int n) {
 
 struct Layout {
   size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, tobs, coef, spec, staging,
-      total;
+      rinv, total;
   size_t spec_elems, spec_stride;
   int n_wg_split, n_wg_whole;   // x-pass workgroups (one shell partial each) per path
   int n_wg_max;
@@ -124,6 +124,7 @@ Layout make_layout(const mf_chain_desc& d) {
   L.coef = take(nc * 2 * m * rs);
   L.spec = take(nc * L.spec_stride * 2 * rs);
   L.staging = take(m * rs);
+  L.rinv = take(d.has_response ? nc * m * 8 : 0);   // 1 / R per voxel (0 unobserved), FP64
   L.total = off;
   return L;
 }
@@ -143,6 +144,8 @@ mf_status check_desc(const mf_chain_desc* d) {
   if (d->sample_pk != 0 && d->sample_pk != 1)
     return fail(MF_E_INVALID_ARG, "sample_pk must be 0 or 1");
   if (std::isnan(d->tau)) return fail(MF_E_INVALID_ARG, "tau is NaN");
+  if (d->has_response != 0 && d->has_response != 1)
+    return fail(MF_E_INVALID_ARG, "has_response must be 0 or 1");
   return MF_OK;
 }
 
@@ -439,15 +442,32 @@ mf_status download_real(mf_problem* p, double* dst, const void* src, size_t coun
   return MF_OK;
 }
 
+// Voxel i is observed when its noise variance is finite and its response
+// (1 without one) is not zero.
+bool observed(const double* noise_var, const double* response, size_t i) {
+  return !std::isinf(noise_var[i]) && (!response || response[i] != 0.0);
+}
+
+// Messenger coefficients of Sec. 3.1 with T = tau and N~ = N - tau R^2:
+// mean = alpha s + beta with alpha = N~ / N = 1 - tau R^2 / N and
+// beta = tau R d / N; (1, 0) where unobserved.  alpha is 0 in exact
+// arithmetic where N / R^2 is smallest (tau is that minimum); rounding of
+// tau R^2 / N there can leave -1 ulp, which is set back to 0.
 template <typename R, int N>
 void permute_coef(std::vector<R>& out, std::vector<uint8_t>& obs, const double* data,
-                  const double* noise_var, double tau) {
+                  const double* noise_var, const double* response, double tau) {
   using T = mf::ZTile<R, N>;
   const int tiles = (N / T::IXB) * (N / T::P);
   out.assign(static_cast<size_t>(2) * N * N * N, R(0));
   obs.assign(tiles, 0);
-  auto alpha = [&](size_t i) { return std::isinf(noise_var[i]) ? 1.0 : 1.0 - tau / noise_var[i]; };
-  auto beta = [&](size_t i) { return std::isinf(noise_var[i]) ? 0.0 : tau * data[i] / noise_var[i]; };
+  auto resp = [&](size_t i) { return response ? response[i] : 1.0; };
+  auto alpha = [&](size_t i) {
+    return observed(noise_var, response, i)
+               ? std::max(0.0, 1.0 - tau * resp(i) * resp(i) / noise_var[i]) : 1.0;
+  };
+  auto beta = [&](size_t i) {
+    return observed(noise_var, response, i) ? tau * resp(i) * data[i] / noise_var[i] : 0.0;
+  };
   for (int tile = 0; tile < tiles; ++tile)
     for (int e = 0; e < T::EPT; ++e)
       for (int tid = 0; tid < T::NT; ++tid) {
@@ -459,18 +479,18 @@ void permute_coef(std::vector<R>& out, std::vector<uint8_t>& obs, const double* 
         o[1] = static_cast<R>(alpha(vb));
         o[2] = static_cast<R>(beta(va));
         o[3] = static_cast<R>(beta(vb));
-        if (!std::isinf(noise_var[va]) || !std::isinf(noise_var[vb])) obs[tile] = 1;
+        if (observed(noise_var, response, va) || observed(noise_var, response, vb)) obs[tile] = 1;
       }
 }
 
 template <typename R>
 mf_status upload_coef(mf_problem* p, int c, const double* data, const double* noise_var,
-                      double tau, hipStream_t st) {
+                      const double* response, double tau, hipStream_t st) {
   std::vector<R> buf;
   std::vector<uint8_t> obs;
   switch (p->desc.n) {
 #define MF_PERMUTE(NN) \
-  case NN: permute_coef<R, NN>(buf, obs, data, noise_var, tau); break;
+  case NN: permute_coef<R, NN>(buf, obs, data, noise_var, response, tau); break;
     MF_PERMUTE(8) MF_PERMUTE(16) MF_PERMUTE(32) MF_PERMUTE(48) MF_PERMUTE(64) MF_PERMUTE(80)
     MF_PERMUTE(96) MF_PERMUTE(128) MF_PERMUTE(256) MF_PERMUTE(512)
 #undef MF_PERMUTE
@@ -528,9 +548,10 @@ mf_status mf_workspace_bytes(const mf_chain_desc* desc, size_t* bytes) {
 }
 
 mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
-                          const double* const* noise_var, const double* const* pk_init,
-                          const double* const* s_init, void* workspace, size_t workspace_bytes,
-                          void* stream, mf_problem** out) {
+                          const double* const* noise_var, const double* const* response,
+                          const double* const* pk_init, const double* const* s_init,
+                          void* workspace, size_t workspace_bytes, void* stream,
+                          mf_problem** out) {
   if (!out) return fail(MF_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   mf_status st = check_desc(desc);
@@ -540,6 +561,13 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
   for (int c = 0; c < nch; ++c)
     if (!data[c] || !noise_var[c] || !pk_init[c])
       return fail(MF_E_INVALID_ARG, "input array of chain %d is NULL", c);
+  if (desc->has_response) {
+    if (!response) return fail(MF_E_INVALID_ARG, "has_response = 1 but response is NULL");
+    for (int c = 0; c < nch; ++c)
+      if (!response[c]) return fail(MF_E_INVALID_ARG, "response of chain %d is NULL", c);
+  } else if (response) {
+    return fail(MF_E_INVALID_ARG, "a response is given but has_response = 0");
+  }
   const Layout L = make_layout(*desc);
   if (!workspace) return fail(MF_E_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
@@ -549,25 +577,30 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
 
   const size_t m = static_cast<size_t>(n) * n * n;
   const double vc = std::pow(desc->box / n, 3);
-  // tau per chain and input checks (Sec. 2: 0 < tau <= N_i on observed voxels)
+  // tau per chain and input checks (Sec. 2: 0 < tau <= N_i / R_i^2 on
+  // observed voxels)
   std::vector<double> tau(nch);
   for (int c = 0; c < nch; ++c) {
+    const double* resp = response ? response[c] : nullptr;
     double tmin = std::numeric_limits<double>::infinity();
     size_t n_obs = 0;
     for (size_t i = 0; i < m; ++i) {
       const double nv = noise_var[c][i];
-      if (std::isinf(nv) && nv > 0) continue;
+      const double rr = resp ? resp[i] : 1.0;
+      if (!std::isfinite(rr))
+        return fail(MF_E_NONFINITE, "chain %d voxel %zu: response not finite", c, i);
+      if (rr == 0.0 || (std::isinf(nv) && nv > 0)) continue;
       if (!(nv > 0.0) || !std::isfinite(nv))
         return fail(MF_E_NONFINITE, "chain %d voxel %zu: noise variance %g not > 0", c, i, nv);
       if (!std::isfinite(data[c][i]))
         return fail(MF_E_NONFINITE, "chain %d voxel %zu: data not finite", c, i);
-      tmin = std::min(tmin, nv);
+      tmin = std::min(tmin, nv / (rr * rr));
       ++n_obs;
     }
     if (n_obs == 0) return fail(MF_E_INVALID_ARG, "chain %d has no observed voxel", c);
     if (desc->tau > 0.0) {
       if (desc->tau > tmin)
-        return fail(MF_E_TAU, "tau %g exceeds the smallest observed noise variance %g of chain %d",
+        return fail(MF_E_TAU, "tau %g exceeds the smallest observed N / R^2 (%g) of chain %d",
                     desc->tau, tmin, c);
       tau[c] = desc->tau;
     } else {
@@ -606,12 +639,25 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
           hipSuccess ||
       hipStreamSynchronize(hs) != hipSuccess)
     return cleanup(fail(MF_E_DEVICE, "uploading tables failed"));
-  // messenger coefficients in FP64 (alpha = 1 - tau/N, beta = tau d / N),
-  // rounded once and stored in the z-pass thread order
+  // messenger coefficients in FP64 (alpha = 1 - tau R^2 / N,
+  // beta = tau R d / N), rounded once and stored in the z-pass thread order
   for (int c = 0; c < nch; ++c) {
-    st = p->fp64() ? upload_coef<double>(p, c, data[c], noise_var[c], tau[c], hs)
-                   : upload_coef<float>(p, c, data[c], noise_var[c], tau[c], hs);
+    const double* resp = response ? response[c] : nullptr;
+    st = p->fp64() ? upload_coef<double>(p, c, data[c], noise_var[c], resp, tau[c], hs)
+                   : upload_coef<float>(p, c, data[c], noise_var[c], resp, tau[c], hs);
     if (st != MF_OK) return cleanup(st);
+  }
+  // 1 / R per voxel (0 where unobserved), used by the Wiener filter only
+  if (desc->has_response) {
+    std::vector<double> ri(m);
+    for (int c = 0; c < nch; ++c) {
+      for (size_t i = 0; i < m; ++i)
+        ri[i] = observed(noise_var[c], response[c], i) ? 1.0 / response[c][i] : 0.0;
+      if (hipMemcpyAsync(p->ws + L.rinv + static_cast<size_t>(c) * m * 8, ri.data(), m * 8,
+                         hipMemcpyHostToDevice, hs) != hipSuccess ||
+          hipStreamSynchronize(hs) != hipSuccess)
+        return cleanup(fail(MF_E_DEVICE, "uploading the response failed"));
+    }
   }
   // initial state
   const size_t rs = p->fp64() ? 8 : 4;
@@ -1017,7 +1063,7 @@ namespace {
 // Wiener workspace for nc chains processed together; every buffer holds the
 // chains one after another, each 256-byte aligned.
 struct WLayout {
-  size_t partial, pkg, gacc, table, wcoef, fwd, adj, ckpt, aux, acc, total;
+  size_t partial, pkg, gacc, table, wcoef, fwd, adj, ckpt, aux, acc, dr, total;
   size_t spec_bytes;   // one chain's spectrum (with the problem's stride)
   int nblk, n_ckpt, nc;
 };
@@ -1047,6 +1093,7 @@ WLayout wiener_layout(const mf_problem* p, int n_iter, int every, int nc) {
   W.ckpt = take(static_cast<size_t>(W.n_ckpt) * specs);
   W.aux = take(static_cast<size_t>(every) * specs);
   W.acc = take(nc * m * rs);
+  W.dr = take(p->desc.has_response ? nc * m * 8 : 0);   // d / R
   W.total = off;
   return W;
 }
@@ -1145,12 +1192,28 @@ mf_status wiener_iter(mf_problem* p, mf::SweepArgs<R> a, int nc, mf::cx<R>* spec
   return MF_OK;
 }
 
+// y = x / R for chains c0 .. c0 + nc - 1 (y may be x).  A problem with a
+// response R is the problem with data d / R and noise N / R^2, voxel by
+// voxel: the iteration, s_K and chi2_K coincide, and d chi2 / d d is
+// d chi2 / d (d / R) divided by R.
+void scale_by_rinv(const mf_problem* p, int c0, int nc, const double* x, double* y, hipStream_t st) {
+  const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  const double* rinv = reinterpret_cast<const double*>(p->ws + p->L.rinv) + static_cast<size_t>(c0) * m;
+  hipLaunchKernelGGL(mf::scale_kernel, dim3(1024), dim3(256), 0, st, x, rinv, y,
+                     static_cast<size_t>(nc) * m);
+}
+
 template <typename R>
 mf_status wiener_forward(mf_problem* p, int c0, const double* d, const double* pk, int n_iter,
                          int every, char* g, const WLayout& W, double* chi2, double* s_out,
                          hipStream_t st) {
   const int n = p->desc.n, nb = p->desc.n_bins, nc = W.nc;
   const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
+  if (p->desc.has_response) {
+    double* dr = reinterpret_cast<double*>(g + W.dr);
+    scale_by_rinv(p, c0, nc, d, dr, st);
+    d = dr;
+  }
   const double vcell = std::pow(p->desc.box / n, 3);
   auto a = wiener_args<R>(p, c0, g, W);
   const size_t specs = static_cast<size_t>(nc) * W.spec_bytes;
@@ -1212,6 +1275,11 @@ mf_status wiener_backward(mf_problem* p, int c0, const double* d, char* g, const
   R* acc = reinterpret_cast<R*>(g + W.acc);
   auto slot = [&](int j) { return reinterpret_cast<mf::cx<R>*>(g + W.aux + static_cast<size_t>(j) * specs); };
   const R* s = reinterpret_cast<const R*>(p->ws + p->L.staging);
+  if (p->desc.has_response) {
+    double* dr = reinterpret_cast<double*>(g + W.dr);
+    scale_by_rinv(p, c0, nc, d, dr, st);
+    d = dr;
+  }
   hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1), dim3(256), 0, st,
                      reinterpret_cast<double*>(g + W.gacc), static_cast<size_t>(nc) * nb);
   hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st, acc, nc * m);
@@ -1271,6 +1339,7 @@ mf_status wiener_backward(mf_problem* p, int c0, const double* d, char* g, const
                        reinterpret_cast<const double*>(g + W.pkg) + c * nb, p->tau[c0 + c], vcell,
                        nb, grad_pk + c * nb);
   }
+  if (p->desc.has_response) scale_by_rinv(p, c0, nc, grad_d, grad_d, st);
   return check_launch("Wiener gradient");
 }
 

@@ -65,6 +65,15 @@ __global__ void wiener_table_kernel(const double* pk, double* pkg, R* table, dou
   table[2 * b + 1] = R(0);
 }
 
+// y = x * w element by element (y may be x).  With w = 1 / R (0 where
+// unobserved) it maps data d to d / R, and a gradient with respect to d / R
+// to one with respect to d.
+__global__ void scale_kernel(const double* x, const double* w, double* y, size_t n) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    y[i] = x[i] * w[i];
+}
+
 template <typename T>
 __global__ void fill_zero_kernel(T* p, size_t n) {
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;

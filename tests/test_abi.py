@@ -110,6 +110,44 @@ def test_init_validation_happens_on_the_host(lib):
     assert "workspace" in binding.mf_last_error()
 
 
+def test_response_validation_happens_on_the_host(lib):
+    w = workloads.small_workload(8, 4)
+    pb = workloads.make_problem(w)
+    m = 8 ** 3
+    plain = binding.make_desc(8, 4, w.box, 1, "fp64")
+    with_r = binding.make_desc(8, 4, w.box, 1, "fp64", has_response=True)
+    # the 1 / R array (FP64 per voxel) only with a response
+    assert binding.mf_workspace_bytes(with_r) >= binding.mf_workspace_bytes(plain) + 8 * m
+    resp = np.full((8,) * 3, 0.5)
+
+    def init(desc, response):
+        return binding.mf_init_problem(desc, [pb["data"]], [pb["noise_var"]], [pb["pk_init"]],
+                                       None, 256, 1 << 40, stream=0, response=response)
+    for desc, response in ((plain, [resp]), (with_r, None)):
+        with pytest.raises(binding.MFError) as e:
+            init(desc, response)
+        assert e.value.status == binding.MF_E_INVALID_ARG
+    bad = resp.copy()
+    bad[3, 3, 3] = np.nan
+    with pytest.raises(binding.MFError) as e:
+        init(with_r, [bad])
+    assert e.value.status == binding.MF_E_NONFINITE
+    # the tau bound is min N / R^2 = 4 min N here
+    tmin = pb["noise_var"][np.isfinite(pb["noise_var"])].min()
+    with_r.tau = 4.0 * tmin * 1.01
+    with pytest.raises(binding.MFError) as e:
+        init(with_r, [resp])
+    assert e.value.status == binding.MF_E_TAU
+    assert "N / R^2" in binding.mf_last_error()
+    with_r.tau = 0.0
+    with pytest.raises(binding.MFError) as e:
+        init(with_r, [np.zeros((8,) * 3)])
+    assert e.value.status == binding.MF_E_INVALID_ARG        # R = 0 everywhere: nothing observed
+    with_r.has_response = 2
+    with pytest.raises(binding.MFError):
+        binding.mf_workspace_bytes(with_r)
+
+
 def test_null_handles_are_rejected(lib):
     assert lib.mf_gibbs_sweep(None, 1, None) == binding.MF_E_INVALID_ARG
     assert lib.mf_get_chain_state(None, 0, None, None, None, None) == binding.MF_E_INVALID_ARG
