@@ -79,10 +79,17 @@ def cpu_baseline(w, pb, max_seconds: float = 30.0):
     for _ in range(n_timed):
         st = sampler.sweep(prob, st)
     dt = time.perf_counter() - t0
+    # the same sweep with every draw replaced by its mean (no Philox, no P
+    # draw): what the oracle spends outside its random numbers
+    t0 = time.perf_counter()
+    sampler.sweep(prob, st, noise=False)
+    dt_det = time.perf_counter() - t0
     return {"value": n_timed / dt, "unit": "sweeps/s", "cores": ncores, "kind": "oracle",
+            "no_rng_value": 1.0 / dt_det,
             "sample": f"{n_timed} FP64 oracle sweeps of the same {w.n}^3 problem after one "
                       f"warm-up sweep (numpy Philox single-threaded, scipy.fft with "
-                      f"{ncores} workers)"}
+                      f"{ncores} workers); no_rng_value: one sweep with every draw "
+                      f"replaced by its mean"}
 
 
 def bench_batched(args):
