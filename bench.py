@@ -528,7 +528,11 @@ def main():
                     "traffic": traffic, "kernel": dom,
                     "algorithmic_bytes_per_launch": alg[dom],
                     "algorithmic_bytes": alg,
-                    "kernel_ms": {k: round(v, 5) for k, v in kernel_ms.items()}}
+                    "kernel_ms": {k: round(v, 5) for k, v in kernel_ms.items()},
+                    # every pass priced the same way (the dominant one is the
+                    # longest; the z- and x-passes are within a few percent)
+                    "per_kernel_frac": {k: round(alg[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                        for k, v in kernel_ms.items()}}
     smp.close()
     fp64 = None if args.no_fp64_compare else fp64_sweep_rate(w, pb, min(args.steps, 100))
 
