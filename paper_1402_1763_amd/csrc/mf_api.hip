@@ -59,17 +59,17 @@ enum XPath : int { kPathSplit = 0, kPathWhole = 1 };
 
 template <typename R, int N>
 struct Geometry {
-  static constexpr int split_columns() {
-    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N>::P;
-    else return mf::XTile<R, N>::P;
+  static constexpr int split_wpp() {
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N>::WPP;
+    else return N / mf::XTile<R, N>::P;
   }
-  static constexpr int xp_split = split_columns();
-  static constexpr int xp_whole = mf::XTile<R, N>::P;
+  static constexpr int xp_split = split_wpp();
+  static constexpr int xp_whole = N / mf::XTile<R, N>::P;
   static constexpr int ztiles = (N / mf::ZTile<R, N>::IXB) * (N / mf::ZTile<R, N>::P);
 };
 
 struct Shape {
-  int xp_split, xp_whole;   // columns per x-pass workgroup on each path
+  int xp_split, xp_whole;   // x-pass workgroups per kz plane on each path
   int ztiles;               // z-pass tiles per chain
 };
 
@@ -101,8 +101,8 @@ Layout make_layout(const mf_chain_desc& d) {
   Layout L{};
   L.spec_elems = (n / 2 + 1) * n * n;
   L.spec_stride = align_up(L.spec_elems * 2 * rs) / (2 * rs);
-  L.n_wg_split = static_cast<int>((n / 2 + 1) * (n / sh.xp_split));
-  L.n_wg_whole = static_cast<int>((n / 2 + 1) * (n / sh.xp_whole));
+  L.n_wg_split = static_cast<int>((n / 2 + 1) * sh.xp_split);
+  L.n_wg_whole = static_cast<int>((n / 2 + 1) * sh.xp_whole);
   L.n_wg_max = std::max(L.n_wg_split, L.n_wg_whole);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -329,17 +329,17 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
       break;
     case kXDetK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet>), dim3(N / XS::P, N / 2 + 1, nch),
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet>), dim3(XS::WPP, N / 2 + 1, nch),
                            dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kXMixK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXMix>), dim3(N / XS::P, N / 2 + 1, nch),
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXMix>), dim3(XS::WPP, N / 2 + 1, nch),
                            dim3(XS::NT), 2 * XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kXMixInvK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xmixinv_kernel<R, N>), dim3(N / XS::P, N / 2 + 1, nch), dim3(XS::NT),
+        hipLaunchKernelGGL((mf::xmixinv_kernel<R, N>), dim3(XS::WPP, N / 2 + 1, nch), dim3(XS::NT),
                            a.nb * sizeof(R) + (a.nb + 1) * 4, st, a);
       break;
     case kMixPkK:
@@ -347,13 +347,13 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
       break;
     case kXAdjK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXAdj>), dim3(N / XS::P, N / 2 + 1, nch),
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXAdj>), dim3(XS::WPP, N / 2 + 1, nch),
                            dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
       break;
     case kX:
       if constexpr (can_split) {
         if (split) {
-          hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample>), dim3(N / XS::P, N / 2 + 1, nch),
+          hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample>), dim3(XS::WPP, N / 2 + 1, nch),
                              dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
           break;
         }
