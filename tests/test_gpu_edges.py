@@ -1,0 +1,79 @@
+"""GPU edge cases: zero sweeps, and the largest bin count (1024 bins, most of
+them empty at small |k|) on the 256^3 grid, where the per-wave FP64 shell
+histograms need the most LDS: about 78 KB per x-pass workgroup for an FP32
+Gibbs sweep and 152 KB for an FP64 mixing sweep."""
+import numpy as np
+import pytest
+
+from oracle import mixing, sampler, shells
+from paper_1402_1763_amd import binding, workloads
+from tests.gpu_util import TOL, errors, gpu_sampler, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.load()
+    torch.cuda.set_device(0)
+
+
+def test_zero_sweeps_leave_the_state_alone():
+    w = workloads.small_workload(32, 8, precision="fp64", seed=81, rng_seed=82)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    s0 = np.random.default_rng(3).standard_normal((32,) * 3)
+    smp.set_state(0, s0, pb["pk_init"], 0)
+    smp.sweep(0)
+    smp.mixing_sweep(0)
+    s, pk, n_done = smp.state()
+    smp.close()
+    assert n_done == 0
+    assert np.abs(s - s0).max() < 1e-12 * np.abs(s0).max()     # up to the z-transform round trip
+    assert np.allclose(pk, pb["pk_init"], rtol=1e-15, atol=0)
+
+
+def _max_bins_problem(precision):
+    n, nb = 256, 1024
+    w = workloads.small_workload(n, nb, precision=precision, seed=91, rng_seed=92, box=2000.0)
+    pb = workloads.make_problem(w)
+    counts = shells.mode_counts(n, nb)
+    assert (counts == 0).sum() > 0 and counts.sum() == n ** 3 - 1
+    return w, pb, counts
+
+
+def test_maximum_bins_gibbs_fp32():
+    w, pb, counts = _max_bins_problem("fp32")
+    print(f"1024 bins at 256^3 FP32: {(counts == 0).sum()} empty bins", flush=True)
+    smp = gpu_sampler(w, pb)
+    smp.sweep(2)
+    s_gpu, p_gpu, _ = smp.state()
+    smp.close()
+    prob = oracle_problem(w, pb)
+    st = sampler.run_chain(prob, sampler.State(s=np.zeros((256,) * 3),
+                                               p_grid=pb["pk_init"] / w.cell_volume), 2)
+    p_ref = st.p_grid * w.cell_volume
+    err_s, err_p = errors(s_gpu, p_gpu, st.s, p_ref)
+    print(f"  err_s={err_s:.2e} err_P={err_p:.2e}", flush=True)
+    assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
+    # empty bins keep P (stored in grid units, P / V_cell, so up to rounding)
+    assert np.allclose(p_gpu[counts == 0], pb["pk_init"][counts == 0], rtol=1e-14, atol=0)
+
+
+def test_maximum_bins_mixing_fp64():
+    w, pb, counts = _max_bins_problem("fp64")
+    smp = gpu_sampler(w, pb)
+    smp.sweep(1)
+    smp.mixing_sweep(1)
+    s_gpu, p_gpu, _ = smp.state()
+    smp.close()
+    prob = oracle_problem(w, pb)
+    st = sampler.run_chain(prob, sampler.State(s=np.zeros((256,) * 3),
+                                               p_grid=pb["pk_init"] / w.cell_volume), 1)
+    st = mixing.mixing_sweep(prob, st)
+    err_s, err_p = errors(s_gpu, p_gpu, st.s, st.p_grid * w.cell_volume)
+    print(f"1024 bins at 256^3 FP64 mixing: err_s={err_s:.2e} err_P={err_p:.2e}", flush=True)
+    assert err_s < TOL["fp64"] and err_p < TOL["fp64"]
