@@ -393,6 +393,14 @@ def bench_wiener(args, chains: int = 1):
     torch.cuda.synchronize()
     fwd_ms, bwd_ms = start.elapsed_time(mid), mid.elapsed_time(stop)
     assert bool(torch.isfinite(chi2).all()) and bool(torch.isfinite(gp).all())
+    # the log-determinant term's trace estimator: 4 probes of n_iter iterations
+    wf.logdet_trace(pk, 1)
+    start.record(stream)
+    tr = wf.logdet_trace(pk, 4)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    logdet_probe_ms = start.elapsed_time(stop) / 4
+    assert bool(torch.isfinite(tr).all())
     gibbs_ms = plain_sweep_ms(w, pb, 200)
     spec = 8 * (w.n // 2 + 1) * w.n ** 2
     coef_frac = (smp.sweep_bytes()["zpass"] - 2 * spec * chains) / (8 * w.m * chains)
@@ -407,6 +415,7 @@ def bench_wiener(args, chains: int = 1):
         "config": {"workload": args.workload, "n": w.n, "n_bins": w.n_bins, "chains": chains,
                    "iterations": n_iter, "ckpt_every": every,
                    "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
+                   "logdet_trace_ms_per_probe": round(logdet_probe_ms, 4),
                    "iterations_per_s": round(3 * n_iter * chains * 1000.0 / ms, 1),
                    "plain_gibbs_sweep_ms": round(gibbs_ms, 5),
                    "iteration_cost_vs_gibbs_sweep": round(ms / (3 * n_iter * chains) / gibbs_ms, 3),

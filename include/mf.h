@@ -295,6 +295,36 @@ mf_status mf_wiener_forward(mf_problem* p, int32_t chain, const double* d, const
 mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void* workspace,
                              size_t ws_bytes, double* grad_d, double* grad_pk, void* stream);
 
+/* The log-determinant term of the likelihood's power-spectrum gradient (grid
+ * sides 32 to 256).  The data d = R s + eps of Sec. 2 are Gaussian with
+ * covariance A = (R S R + N) over the observed voxels, so
+ *   d ln L / d P_b = -1/2 d chi2_inf / d P_b - 1/2 T_b,
+ *   T_b = tr(A^-1 R (dS/dP_b) R),
+ * where chi2_inf is the converged chi2_K of mf_wiener_forward (whose P-gradient
+ * mf_wiener_backward gives).  mf_wiener_logdet_trace estimates T_b by
+ * Hutchinson's method with probes of covariance N: z = sgn(R) sqrt(N) xi on
+ * observed voxels, xi = +-1 from Philox counter (v div 4, probe, 4, chain_id +
+ * chain), word v mod 4 (top bit set -> -1) for voxel v in [ix][iy][iz] order.
+ * Each probe is filtered by K messenger iterations (as in mf_wiener_forward),
+ * u = N^-1 (z - R s_K) -> A^-1 z, and contributes
+ *   (1/M) sum over the modes of bin b of Re(conj(FT(R u)) FT(R z / N)),
+ * whose expectation is T_b once the filter has converged.
+ *   pk: device FP64, n_bins per chain, physical units.
+ *   trace_out: device FP64, n_bins per chain: the mean over probes probe0 ..
+ *     probe0 + n_probes - 1, per unit of physical P_b.
+ * chain = -1 runs every chain in the same launches.  The workspace (size from
+ * mf_wiener_logdet_workspace_bytes, 256-byte aligned) holds the probe
+ * coefficients and four spectra per chain.  One probe costs K + 3 iterations.
+ * Enqueues on `stream`; uses the problem's shell partials as scratch, so it
+ * must not overlap sweeps on the same problem.  The chains' Gibbs state is
+ * not touched.
+ * Errors: MF_E_UNSUPPORTED_SIZE, MF_E_STATE (bad chain), MF_E_INVALID_ARG
+ * (n_iter or n_probes < 1, NULL pointers), MF_E_WORKSPACE, MF_E_DEVICE. */
+mf_status mf_wiener_logdet_workspace_bytes(const mf_problem* p, int32_t chain, size_t* bytes);
+mf_status mf_wiener_logdet_trace(mf_problem* p, int32_t chain, const double* pk, int32_t n_iter,
+                                 int32_t n_probes, uint32_t probe0, void* workspace,
+                                 size_t ws_bytes, double* trace_out, void* stream);
+
 /* Chain diagnostics (Sec. 4.3).
  *
  * Recording.  mf_set_diagnostics makes sweeps record sample n, the chain

@@ -95,6 +95,12 @@ SIGNATURES = {
     "mf_wiener_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "mf_wiener_logdet_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_wiener_logdet_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "mf_diagnostics_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t),
                                             ctypes.POINTER(ctypes.c_size_t)]),
@@ -537,6 +543,31 @@ class WienerFilter:
                           self.sampler.stream.cuda_stream)
         self.generation += 1
         return chi2, s
+
+    def logdet_trace(self, pk, n_probes: int, probe0: int = 0):
+        """Hutchinson estimate of T_b = tr(A^-1 R (dS/dP_b) R), A = R S R + N
+        on the observed voxels, the log-determinant term of the likelihood's
+        P-gradient: d ln L/d P_b = -1/2 d chi2/d P_b - 1/2 T_b.  Mean over
+        probes probe0 .. probe0 + n_probes - 1, each filtered by n_iter
+        messenger iterations; per unit of physical P_b."""
+        import torch
+        n, nb = self.sampler.n, self.sampler.n_bins
+        if (pk.dtype != torch.float64 or not pk.is_cuda or tuple(pk.shape) != self._lead() + (nb,)
+                or not pk.is_contiguous()):
+            raise ValueError(f"pk must be a contiguous float64 cuda tensor of shape {self._lead() + (nb,)}")
+        out = ctypes.c_size_t(0)
+        _check(load().mf_wiener_logdet_workspace_bytes(ctypes.c_void_p(self.sampler.handle),
+                                                       self.chain, ctypes.byref(out)))
+        if getattr(self, "_ld_bytes", 0) < out.value:
+            self._ld_ws = torch.empty(out.value + 256, dtype=torch.uint8, device=pk.device)
+            self._ld_bytes = out.value
+        ptr = (self._ld_ws.data_ptr() + 255) // 256 * 256
+        trace = torch.empty(self._lead() + (nb,), dtype=torch.float64, device=pk.device)
+        _check(load().mf_wiener_logdet_trace(
+            ctypes.c_void_p(self.sampler.handle), self.chain, ctypes.c_void_p(pk.data_ptr()),
+            self.n_iter, n_probes, probe0, ctypes.c_void_p(ptr), self._ld_bytes,
+            ctypes.c_void_p(trace.data_ptr()), ctypes.c_void_p(self.sampler.stream.cuda_stream)))
+        return trace
 
     def backward(self, d):
         """(d chi2/d d, d chi2/d pk) of the last forward run (same d)."""

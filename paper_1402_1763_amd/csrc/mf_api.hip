@@ -1147,12 +1147,13 @@ void with_n(int n, F&& f) {
 // Sweep arguments of the deterministic iteration of chains c0 .. c0 + nc - 1
 // (grid z = nc; chain c of the launch is problem chain c0 + c).
 template <typename R>
-mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, char* g, const WLayout& W) {
+mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, const R* coef, R* table, double* pkg,
+                             double* gacc) {
   mf::SweepArgs<R> a = args_of<R>(p, kPathSplit);
-  a.coef = reinterpret_cast<const R*>(g + W.wcoef);
-  a.table = reinterpret_cast<R*>(g + W.table);
-  a.pk = reinterpret_cast<double*>(g + W.pkg);
-  a.gacc = reinterpret_cast<double*>(g + W.gacc);
+  a.coef = coef;
+  a.table = table;
+  a.pk = pkg;
+  a.gacc = gacc;
   a.tau = reinterpret_cast<const double*>(p->ws + p->L.tau) + c0;
   a.status = reinterpret_cast<uint32_t*>(p->ws + p->L.status) + c0;
   a.tile_obs = reinterpret_cast<const uint8_t*>(p->ws + p->L.tobs) + static_cast<size_t>(c0) * p->sh.ztiles;
@@ -1162,6 +1163,13 @@ mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, char* g, const WLayout
   a.trace = nullptr;
   a.mom = nullptr;
   return a;
+}
+
+template <typename R>
+mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, char* g, const WLayout& W) {
+  return wiener_args<R>(p, c0, reinterpret_cast<const R*>(g + W.wcoef),
+                        reinterpret_cast<R*>(g + W.table), reinterpret_cast<double*>(g + W.pkg),
+                        reinterpret_cast<double*>(g + W.gacc));
 }
 
 mf_status check_launch(const char* what) {
@@ -1390,6 +1398,150 @@ mf_status mf_wiener_backward(mf_problem* p, int32_t chain, const double* d, void
   char* g = static_cast<char*>(workspace);
   return p->fp64() ? wiener_backward<double>(p, c0, d, g, W, grad_d, grad_pk, hs)
                    : wiener_backward<float>(p, c0, d, g, W, grad_d, grad_pk, hs);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- log-determinant trace
+namespace {
+
+// Workspace of the trace estimator for nc chains: the filter table, two sets
+// of bin sums, the probe coefficients and four spectra (s_K, s_{K-1}, the
+// transform of beta_z, scratch).
+struct LLayout {
+  size_t pkg, table, g1, g0, wcoef, fwd, prev, aux, scr, total;
+  size_t specs;   // bytes of nc spectra
+  int nc;
+};
+
+LLayout logdet_layout(const mf_problem* p, int nc) {
+  const size_t rs = p->fp64() ? 8 : 4;
+  const size_t n = p->desc.n, m = n * n * n, nb = p->desc.n_bins;
+  LLayout L{};
+  L.nc = nc;
+  L.specs = static_cast<size_t>(nc) * p->L.spec_stride * 2 * rs;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.pkg = take(nc * nb * 8);
+  L.table = take(nc * nb * 2 * rs);
+  L.g1 = take(nc * nb * 8);
+  L.g0 = take(nc * nb * 8);
+  L.wcoef = take(nc * 2 * m * rs);
+  L.fwd = take(L.specs);
+  L.prev = take(L.specs);
+  L.aux = take(L.specs);
+  L.scr = take(L.specs);
+  L.total = off;
+  return L;
+}
+
+// One probe j: K iterations on beta_z from s_0 = 0 (s_{K-1} kept), the
+// transform b^ of beta_z stored by a pass with t = beta_z, then the bin sums
+// G1 = (1/M) sum Re(conj(t^_K) b^) and G0 (the same with t_{K-1}) from two
+// adjoint-mode passes; T_b += (G1 - f G0) / (tau^2 V_cell) / n_probes.
+template <typename R>
+mf_status logdet_run(mf_problem* p, int c0, const double* pk, int n_iter, int n_probes,
+                     uint32_t probe0, char* g, const LLayout& L, double* out, hipStream_t st) {
+  const int n = p->desc.n, nb = p->desc.n_bins, nc = L.nc;
+  const size_t m = static_cast<size_t>(n) * n * n, entries = m / 2;
+  const double vcell = std::pow(p->desc.box / n, 3);
+  const int nblk = static_cast<int>((entries + mf::kWienerThreads - 1) / mf::kWienerThreads);
+  R* wcoef = reinterpret_cast<R*>(g + L.wcoef);
+  double* pkg = reinterpret_cast<double*>(g + L.pkg);
+  double* g1 = reinterpret_cast<double*>(g + L.g1);
+  double* g0 = reinterpret_cast<double*>(g + L.g0);
+  auto a = wiener_args<R>(p, c0, wcoef, reinterpret_cast<R*>(g + L.table), pkg, g1);
+  auto a0 = a;
+  a0.gacc = g0;
+  auto* fwd = reinterpret_cast<mf::cx<R>*>(g + L.fwd);
+  auto* prev = reinterpret_cast<mf::cx<R>*>(g + L.prev);
+  auto* aux = reinterpret_cast<mf::cx<R>*>(g + L.aux);
+  auto* scr = reinterpret_cast<mf::cx<R>*>(g + L.scr);
+  for (int c = 0; c < nc; ++c)
+    hipLaunchKernelGGL((mf::wiener_table_kernel<R>), dim3((nb + 63) / 64), dim3(64), 0, st,
+                       pk + c * nb, pkg + c * nb, reinterpret_cast<R*>(g + L.table) + c * 2 * nb,
+                       p->tau[c0 + c], vcell, static_cast<double>(m), nb);
+  hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1), dim3(256), 0, st, out,
+                     static_cast<size_t>(nc) * nb);
+  mf_status r = check_launch("log-determinant set-up");
+  if (r != MF_OK) return r;
+  for (int j = 0; j < n_probes; ++j) {
+    for (int c = 0; c < nc; ++c) {
+      const R* coef = reinterpret_cast<const R*>(p->ws + p->L.coef) + static_cast<size_t>(c0 + c) * 2 * m;
+      with_n(n, [&](auto nn) {
+        constexpr int N = decltype(nn)::value;
+        hipLaunchKernelGGL((mf::probe_coef_kernel<R, N>), dim3(nblk), dim3(mf::kWienerThreads), 0,
+                           st, coef, wcoef + static_cast<size_t>(c) * 2 * m, p->tau[c0 + c],
+                           probe0 + static_cast<uint32_t>(j), p->desc.chain_id + c0 + c, a.key0,
+                           a.key1, entries);
+      });
+    }
+    hipLaunchKernelGGL((mf::fill_zero_kernel<R>), dim3(1024), dim3(256), 0, st,
+                       reinterpret_cast<R*>(fwd), L.specs / sizeof(R));
+    if ((r = check_launch("log-determinant probe")) != MF_OK) return r;
+    for (int k = 0; k < n_iter; ++k) {
+      if (k == n_iter - 1)
+        MF_HIP(hipMemcpyAsync(prev, fwd, L.specs, hipMemcpyDeviceToDevice, st));
+      if ((r = wiener_iter<R>(p, a, nc, fwd, nullptr, false, R(1), R(1), nullptr, st)) != MF_OK)
+        return r;
+    }
+    MF_HIP(hipMemcpyAsync(scr, fwd, L.specs, hipMemcpyDeviceToDevice, st));
+    if ((r = wiener_iter<R>(p, a, nc, scr, aux, false, R(0), R(1), nullptr, st)) != MF_OK) return r;
+    hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1), dim3(256), 0, st, g1,
+                       static_cast<size_t>(nc) * nb);
+    hipLaunchKernelGGL((mf::fill_zero_kernel<double>), dim3(1), dim3(256), 0, st, g0,
+                       static_cast<size_t>(nc) * nb);
+    MF_HIP(hipMemcpyAsync(scr, fwd, L.specs, hipMemcpyDeviceToDevice, st));
+    if ((r = wiener_iter<R>(p, a, nc, scr, aux, true, R(1), R(1), nullptr, st)) != MF_OK) return r;
+    MF_HIP(hipMemcpyAsync(scr, prev, L.specs, hipMemcpyDeviceToDevice, st));
+    if ((r = wiener_iter<R>(p, a0, nc, scr, aux, true, R(1), R(1), nullptr, st)) != MF_OK) return r;
+    for (int c = 0; c < nc; ++c)
+      hipLaunchKernelGGL(mf::logdet_combine_kernel, dim3((nb + 63) / 64), dim3(64), 0, st,
+                         g1 + c * nb, g0 + c * nb, pkg + c * nb, p->tau[c0 + c], vcell,
+                         1.0 / n_probes, nb, out + c * nb);
+    if ((r = check_launch("log-determinant sums")) != MF_OK) return r;
+  }
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_wiener_logdet_workspace_bytes(const mf_problem* p, int32_t chain, size_t* bytes) {
+  if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
+  int c0 = 0, nc = 0;
+  const mf_status r = wiener_chains(p, chain, &c0, &nc);
+  if (r != MF_OK) return r;
+  *bytes = logdet_layout(p, nc).total;
+  return MF_OK;
+}
+
+mf_status mf_wiener_logdet_trace(mf_problem* p, int32_t chain, const double* pk, int32_t n_iter,
+                                 int32_t n_probes, uint32_t probe0, void* workspace,
+                                 size_t ws_bytes, double* trace_out, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (p->desc.n < 32 || p->desc.n > 256)
+    return fail(MF_E_UNSUPPORTED_SIZE, "the Wiener iteration supports grid sides 32 to 256 (got %d)",
+                p->desc.n);
+  int c0 = 0, nc = 0;
+  mf_status r = wiener_chains(p, chain, &c0, &nc);
+  if (r != MF_OK) return r;
+  if (n_iter < 1 || n_probes < 1) return fail(MF_E_INVALID_ARG, "need n_iter >= 1 and n_probes >= 1");
+  if (!pk || !trace_out) return fail(MF_E_INVALID_ARG, "pk and trace_out must be device pointers");
+  const LLayout L = logdet_layout(p, nc);
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(MF_E_WORKSPACE, "log-determinant workspace NULL or not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(MF_E_WORKSPACE, "log-determinant workspace too small: %zu < %zu", ws_bytes, L.total);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* g = static_cast<char*>(workspace);
+  return p->fp64() ? logdet_run<double>(p, c0, pk, n_iter, n_probes, probe0, g, L, trace_out, hs)
+                   : logdet_run<float>(p, c0, pk, n_iter, n_probes, probe0, g, L, trace_out, hs);
 }
 
 }  // extern "C"

@@ -19,7 +19,13 @@
 
 namespace mf {
 
-enum : uint32_t { kPhaseMessenger = 0, kPhaseSignal = 1, kPhaseGamma = 2, kPhaseMix = 3 };
+enum : uint32_t {
+  kPhaseMessenger = 0,
+  kPhaseSignal = 1,
+  kPhaseGamma = 2,
+  kPhaseMix = 3,
+  kPhaseProbe = 4   // signs of the log-determinant estimator's probes
+};
 constexpr uint32_t kGammaAttempts = 1u << 16;   // counter word 0 = bin * 2^16 + attempt
 
 struct Words4 {

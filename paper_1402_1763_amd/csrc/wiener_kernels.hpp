@@ -4,10 +4,11 @@
 //
 // One iteration maps s_k to s_{k+1} = C (alpha s_k + beta), with
 // C = F^-1 diag(f) F, f_b = P_b / (P_b + tau) per |k| bin, f = 0 at k = 0,
-// alpha = 1 - tau/N_i and beta = tau d_i / N_i on observed voxels, (1, 0)
-// elsewhere (Sec. 3.1: the means of the messenger and signal conditionals).
-// The loss is chi2_K = sum_i w_i d_i (d_i - s_K,i), w_i = 1/N_i (0 where
-// unobserved), which tends to d^T (S + N)^-1 d as K grows.
+// alpha = 1 - tau R_i^2/N_i and beta = tau R_i d_i / N_i on observed voxels,
+// (1, 0) elsewhere (Sec. 3.1: the means of the messenger and signal
+// conditionals).  With R = 1 the loss is chi2_K = sum_i w_i d_i (d_i - s_K,i),
+// w_i = 1/N_i (0 where unobserved), which tends to d^T (S + N)^-1 d as K
+// grows; a response is handled by rescaling d to d / R.
 //
 // The sweep kernels run the iteration in deterministic modes (kZDet, kXDet,
 // kXAdj, kPkGrad).  The kernels here build the iteration's inputs and finish
@@ -72,6 +73,43 @@ __global__ void scale_kernel(const double* x, const double* w, double* y, size_t
   for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x)
     y[i] = x[i] * w[i];
+}
+
+// Probe coefficients of the log-determinant estimator: (alpha, beta_z) with
+// beta_z = tau R z / N for the probe z = sgn(R) sqrt(N) xi, i.e.
+// beta_z = sqrt(tau (1 - alpha)) xi, since 1 - alpha = tau R^2 / N.  xi = +-1
+// of voxel v comes from Philox counter (v div 4, probe, kPhaseProbe, chain),
+// word v mod 4, top bit set -> -1.
+template <typename R, int N>
+__global__ void __launch_bounds__(kWienerThreads)
+probe_coef_kernel(const R* coef, R* wcoef, double tau, uint32_t probe, uint32_t chain,
+                  uint32_t k0, uint32_t k1, size_t entries) {
+  const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
+  if (idx >= entries) return;
+  size_t va = 0, vb = 0;
+  entry_voxels<R, N>(idx, va, vb);
+  auto sign = [&](size_t v) {
+    const Words4 w = philox4x32_10(static_cast<uint32_t>(v >> 2), probe, kPhaseProbe, chain, k0, k1);
+    const uint32_t x = (v & 3) == 0 ? w.x0 : (v & 3) == 1 ? w.x1 : (v & 3) == 2 ? w.x2 : w.x3;
+    return (x >> 31) ? -1.0 : 1.0;
+  };
+  const R aa = coef[idx * 4], ab = coef[idx * 4 + 1];
+  wcoef[idx * 4] = aa;
+  wcoef[idx * 4 + 1] = ab;
+  wcoef[idx * 4 + 2] = static_cast<R>(sqrt(tau * (1.0 - static_cast<double>(aa))) * sign(va));
+  wcoef[idx * 4 + 3] = static_cast<R>(sqrt(tau * (1.0 - static_cast<double>(ab))) * sign(vb));
+}
+
+// out_b += scale (G1_b - f_b G0_b) / (tau^2 V_cell), f_b = P_b / (P_b + tau):
+// one probe's estimate of tr(A^-1 R S_b R) per unit of physical P_b, from the
+// bin sums G1 = (1/M) sum Re(conj(t^_K) b^) and G0 = the same with t_{K-1}
+// (b^ the transform of beta_z; s^_K = f t^_{K-1}).
+__global__ void logdet_combine_kernel(const double* g1, const double* g0, const double* pkg,
+                                      double tau, double vcell, double scale, int nb, double* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double f = pkg[b] / (pkg[b] + tau);
+  out[b] += scale * (g1[b] - f * g0[b]) / (tau * tau * vcell);
 }
 
 template <typename T>

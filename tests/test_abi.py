@@ -152,5 +152,7 @@ def test_null_handles_are_rejected(lib):
     assert lib.mf_gibbs_sweep(None, 1, None) == binding.MF_E_INVALID_ARG
     assert lib.mf_get_chain_state(None, 0, None, None, None, None) == binding.MF_E_INVALID_ARG
     assert lib.mf_graph_launch(None, 1, None) == binding.MF_E_INVALID_ARG
+    assert lib.mf_wiener_logdet_trace(None, 0, None, 1, 1, 0, None, 0, None, None) == binding.MF_E_INVALID_ARG
+    assert lib.mf_wiener_logdet_workspace_bytes(None, 0, None) == binding.MF_E_INVALID_ARG
     lib.mf_destroy_problem(None)
     lib.mf_graph_destroy(None)
