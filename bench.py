@@ -178,6 +178,45 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def hbm_reference(gib: float = 2.0, reps: int = 5) -> dict:
+    """What plain streaming reaches on this GPU, as context for the roofline
+    (whose peak stays the published 8 TB/s): the library's copy and read-only
+    kernels over buffers far larger than the 256 MB last-level cache, each
+    mode at several grid sizes (best kept), and torch's copy for comparison;
+    event-timed."""
+    import torch
+
+    from paper_1402_1763_amd import binding
+    n = int(gib * 2 ** 28)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    sums = torch.empty(65536, dtype=torch.int32, device="cuda")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(reps):
+            fn()
+        stop.record()
+        torch.cuda.synchronize()
+        return nbytes * reps / (start.elapsed_time(stop) * 1e-3) / 1e9
+
+    out = {}
+    for mode in binding.STREAM_MODES:
+        target, nbytes = (dst, 8 * n) if mode.startswith("copy") else (sums, 4 * n)
+        best = max((rate(lambda: binding.stream_reference(src, target, mode, blocks), nbytes), blocks)
+                   for blocks in (1024, 2048, 4096, 8192, 16384))
+        out[f"{mode}_gbs"] = round(best[0], 1)
+        out[f"{mode}_blocks"] = best[1]
+    out["torch_copy_gbs"] = round(rate(lambda: dst.copy_(src), 8 * n), 1)
+    out["buffer_gib"] = gib
+    del src, dst, sums
+    torch.cuda.empty_cache()
+    return out
+
+
 def fp64_sweep_rate(w, pb, steps: int) -> float:
     """Plain FP64 sweeps/s of the same problem on the same GPU (after a
     warm-up and the path autotuner)."""
@@ -544,6 +583,7 @@ def main():
                                         for k, v in kernel_ms.items()}}
     smp.close()
     fp64 = None if args.no_fp64_compare else fp64_sweep_rate(w, pb, min(args.steps, 100))
+    stream_ref = hbm_reference()
 
     out = {
         "metric": "Gibbs sweeps/s at 256^3 FP32 (and % HBM roofline) vs plain FP64 sweep",
@@ -573,6 +613,7 @@ def main():
                                                        / HBM_PEAK_GBS, 4),
                    "wall_s_timed_region": round(wall_s, 4),
                    "fp64_sweeps_per_s": fp64,
+                   "hbm_reference": stream_ref,
                    "speedup_vs_fp64_sweep": (round(1000.0 / ms_per_step / fp64, 3)
                                              if fp64 else None)},
         "roofline": roofline,

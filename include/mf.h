@@ -325,6 +325,18 @@ mf_status mf_wiener_logdet_trace(mf_problem* p, int32_t chain, const double* pk,
                                  int32_t n_probes, uint32_t probe0, void* workspace,
                                  size_t ws_bytes, double* trace_out, void* stream);
 
+/* Streaming reference for the roofline (not part of the sampler): what
+ * plain HBM streaming reaches on the device.  mode 0 copies `bytes` from src
+ * to dst; mode 1 does the same with non-temporal loads and stores; mode 2
+ * reads src and writes one 32-bit sum per workgroup to dst (dst holds at
+ * least 4 * blocks bytes); mode 3 reads with non-temporal loads.  `blocks`
+ * workgroups of 256 threads stride over the buffer, each thread moving four
+ * 16-byte vectors per step.  Enqueues on `stream`.
+ * Errors: MF_E_INVALID_ARG (NULL or unaligned pointers, bytes not a positive
+ * multiple of 16, mode or blocks out of range), MF_E_DEVICE. */
+mf_status mf_stream_reference(const void* src, void* dst, size_t bytes, int32_t mode,
+                              int32_t blocks, void* stream);
+
 /* Chain diagnostics (Sec. 4.3).
  *
  * Recording.  mf_set_diagnostics makes sweeps record sample n, the chain

@@ -101,6 +101,8 @@ SIGNATURES = {
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                               ctypes.c_void_p]),
+    "mf_stream_reference": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "mf_diagnostics_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_size_t),
                                             ctypes.POINTER(ctypes.c_size_t)]),
@@ -579,6 +581,17 @@ class WienerFilter:
                            self.ws_bytes, grad_d.data_ptr(), grad_pk.data_ptr(),
                            self.sampler.stream.cuda_stream)
         return grad_d, grad_pk
+
+
+STREAM_MODES = ("copy", "copy_nt", "read", "read_nt")
+
+
+def stream_reference(src, dst, mode: str, blocks: int, stream=None):
+    """One launch of the streaming reference kernel over src (a cuda tensor)
+    into dst (same size for the copies; >= 4 * blocks bytes for the reads)."""
+    _check(load().mf_stream_reference(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                      src.numel() * src.element_size(), STREAM_MODES.index(mode),
+                                      blocks, ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def acf(trace, max_lag: int, stream=None):

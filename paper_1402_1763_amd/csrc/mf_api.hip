@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "mf.h"
+#include "stream_kernels.hpp"
 #include "sweep_kernels.hpp"
 #include "wiener_kernels.hpp"
 
@@ -1638,6 +1639,27 @@ mf_status mf_acf(const double* trace, int32_t t, int32_t n_bins, int32_t max_lag
   hipLaunchKernelGGL(mf::acf_kernel, dim3(n_bins), dim3(mf::kWienerThreads), 0,
                      static_cast<hipStream_t>(stream), trace, t, n_bins, max_lag, acf, nc);
   return check_launch("acf");
+}
+
+mf_status mf_stream_reference(const void* src, void* dst, size_t bytes, int32_t mode,
+                              int32_t blocks, void* stream) {
+  if (!src || !dst) return fail(MF_E_INVALID_ARG, "src and dst must be device pointers");
+  if (mode < 0 || mode > 3) return fail(MF_E_INVALID_ARG, "mode %d outside 0..3", mode);
+  if (bytes == 0 || bytes % 16 != 0) return fail(MF_E_INVALID_ARG, "bytes must be a positive multiple of 16");
+  if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+    return fail(MF_E_INVALID_ARG, "src and dst must be 16-byte aligned");
+  if (blocks < 1 || blocks > 65536) return fail(MF_E_INVALID_ARG, "blocks %d outside 1..65536", blocks);
+  const auto* s16 = static_cast<const mf::v4u*>(src);
+  const size_t n16 = bytes / 16;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const dim3 grid(static_cast<unsigned>(blocks)), block(mf::kStreamThreads);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(mf::stream_copy_kernel<false>, grid, block, 0, hs, s16, static_cast<mf::v4u*>(dst), n16); break;
+    case 1: hipLaunchKernelGGL(mf::stream_copy_kernel<true>, grid, block, 0, hs, s16, static_cast<mf::v4u*>(dst), n16); break;
+    case 2: hipLaunchKernelGGL(mf::stream_read_kernel<false>, grid, block, 0, hs, s16, static_cast<uint32_t*>(dst), n16); break;
+    default: hipLaunchKernelGGL(mf::stream_read_kernel<true>, grid, block, 0, hs, s16, static_cast<uint32_t*>(dst), n16); break;
+  }
+  return check_launch("stream reference");
 }
 
 }  // extern "C"
