@@ -1,7 +1,9 @@
 """GPU tests of the log-determinant trace estimator (mf_wiener_logdet_trace)
 against the oracle (oracle/logdet.py): the same probes (Philox phase 4 signs)
 give the same per-bin estimates, probe by probe and averaged, for one chain
-and for several chains with responses in one launch."""
+and for several chains with responses in one launch; and, with the chi2
+adjoint, the assembled likelihood gradient behaves as a score (zero mean over
+data drawn at the true P)."""
 import numpy as np
 import pytest
 
@@ -100,3 +102,35 @@ def test_errors():
         binding.WienerFilter(smp, 4, 4, chain=3)
     assert e.value.status == binding.MF_E_STATE
     smp.close()
+
+
+def test_likelihood_gradient_is_a_score_on_the_gpu():
+    """-1/2 (d chi2/d P + T) from mf_wiener_backward and mf_wiener_logdet_trace
+    behaves as the gradient of ln L: eight data sets drawn at the true P (one
+    chain each, one launch) give a mean within noise of zero, and at twice the
+    true P a clearly negative one."""
+    import torch
+    from tests.test_oracle_logdet import _score_data
+    n, nb, k, probes, reals = 32, 6, 200, 32, 8
+    box = 32 * 15.625
+    vcell = (box / n) ** 3
+    p_true = np.array([6.0, 5.0, 4.0, 3.0, 2.0, 1.5])          # grid units, tau = 1
+    mask = np.random.default_rng(1).random((n,) * 3) < 0.25
+    nv = np.where(mask, np.inf, 1.0)
+    ds = [_score_data(n, p_true, mask, 200 + r) for r in range(reals)]
+    smp = binding.Sampler(ds, [nv] * reals, [p_true * vcell] * reals, nb, box, seed=9,
+                          precision="fp64", sample_pk=False)
+    wf = binding.WienerFilter(smp, k, 20, chain=None)
+    d_t = torch.from_numpy(np.stack(ds)).cuda()
+    z = {}
+    for scale in (1.0, 2.0):
+        pk = torch.from_numpy(np.stack([scale * p_true * vcell] * reals)).cuda()
+        wf.forward(d_t, pk)
+        _, grad_pk = wf.backward(d_t)
+        t = wf.logdet_trace(pk, probes)
+        g = (-0.5 * (grad_pk + t)).cpu().numpy()
+        z[scale] = g.mean(axis=0) / (g.std(axis=0, ddof=1) / np.sqrt(reals))
+        print(f"score at {scale} x P_true: z = {np.round(z[scale], 2)}", flush=True)
+    smp.close()
+    assert np.all(np.abs(z[1.0]) < 4.0)
+    assert np.all(z[2.0] < -5.0)

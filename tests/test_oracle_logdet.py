@@ -5,6 +5,8 @@ against dense linear algebra that does not go through the messenger field.
 * probe average              -> dense tr(A^-1 R S_b R) within Monte Carlo error
 * dense trace                -> central differences of the dense ln det A
 * probe signs                -> +-1, balanced, independent across probes and chains
+* -1/2 (d chi2/d P + T)      -> a score: zero mean over data drawn at the true P,
+                                negative at twice the true P
 """
 import numpy as np
 import pytest
@@ -81,3 +83,37 @@ def test_probe_signs_are_balanced_and_independent():
     # neighbouring voxels (same Philox call, different words) are independent too
     flat = a.ravel()
     assert abs(np.mean(flat[0::4] * flat[1::4])) < 4.0 / np.sqrt(m / 4)
+
+
+def _score_data(n, p_grid, mask, seed):
+    """d = s + eps with s Gaussian of bin-constant power p_grid (grid units)
+    and unit white noise on the observed voxels."""
+    from oracle import shells
+    rng = np.random.default_rng(seed)
+    b = shells.bin_of_q(shells.half_grid_q(n), n, len(p_grid))
+    pm = np.where(b >= 0, np.asarray(p_grid)[np.maximum(b, 0)], 0.0)
+    s = np.fft.irfftn(np.fft.rfftn(rng.standard_normal((n,) * 3)) * np.sqrt(pm), s=(n,) * 3,
+                      axes=(0, 1, 2))
+    return np.where(mask, 0.0, s + rng.standard_normal((n,) * 3))
+
+
+@pytest.mark.slow
+def test_likelihood_gradient_is_a_score():
+    """-1/2 (d chi2/d P + T) is the gradient of ln L: over data drawn at the
+    true P its mean is zero, and at twice the true P it points down."""
+    from oracle import adjoint
+    n, k, probes, reals = 16, 120, 16, 8
+    p_true = np.array([6.0, 4.0, 2.5, 1.5])
+    mask = np.random.default_rng(0).random((n,) * 3) < 0.25
+    nv = np.where(mask, np.inf, 1.0)
+    z = {}
+    for scale in (1.0, 2.0):
+        g = []
+        for r in range(reals):
+            prob = sampler.make_problem(_score_data(n, p_true, mask, 100 + r), nv, 4, 250.0, seed=5)
+            _, gp, _ = adjoint.wf_gradient(prob, scale * p_true, k)
+            g.append(-0.5 * (gp + logdet.trace_estimate(prob, scale * p_true, k, range(probes))))
+        g = np.array(g)
+        z[scale] = g.mean(axis=0) / (g.std(axis=0, ddof=1) / np.sqrt(reals))
+    assert np.all(np.abs(z[1.0]) < 4.0), z
+    assert np.all(z[2.0] < -5.0), z
