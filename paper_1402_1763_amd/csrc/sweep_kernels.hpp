@@ -122,6 +122,9 @@ struct ZTile {
   static constexpr int NT = NPEN * N / EPT;
   static constexpr int PSTR = N + 1;
   using TL = Tile<N, NPEN, NT, true, PSTR, 0>;
+  // FP64 at N = 256 would take 256 VGPRs and 8 AGPRs (1 wave per SIMD); held
+  // to 256 registers (2 waves, no spill) the FP64 sweep runs 8% faster.
+  static constexpr int MIN_WAVES = (sizeof(R) == 8 && N == 256) ? 2 : 1;
 };
 
 // y-pass (whole-transform path): NPEN consecutive contiguous pencils of one
@@ -236,7 +239,7 @@ __device__ __forceinline__ float noise_amp(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ double noise_amp(double x) { return sqrt(x); }
 
 template <typename R, int N, int MODE>
-__global__ void __launch_bounds__((ZTile<R, N>::NT))
+__global__ void __launch_bounds__((ZTile<R, N>::NT), (ZTile<R, N>::MIN_WAVES))
 zpass_kernel(SweepArgs<R> a) {
   using T = ZTile<R, N>;
   using TL = typename T::TL;
