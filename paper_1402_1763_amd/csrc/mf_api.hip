@@ -67,18 +67,21 @@ struct Geometry {
   static constexpr int xp_split = split_wpp();
   static constexpr int xp_whole = N / mf::XTile<R, N>::P;
   static constexpr int ztiles = (N / mf::ZTile<R, N>::IXB) * (N / mf::ZTile<R, N>::P);
+  static constexpr int zept = mf::ZTile<R, N>::EPT;
 };
 
 struct Shape {
   int xp_split, xp_whole;   // x-pass workgroups per kz plane on each path
   int ztiles;               // z-pass tiles per chain
+  int zept;                 // elements per z-pass lane (observation bits per tile)
 };
 
 template <typename R>
 Shape shape_of(int n) {
   switch (n) {
 #define MF_SHAPE(NN) \
-  case NN: return Shape{Geometry<R, NN>::xp_split, Geometry<R, NN>::xp_whole, Geometry<R, NN>::ztiles};
+  case NN: return Shape{Geometry<R, NN>::xp_split, Geometry<R, NN>::xp_whole, Geometry<R, NN>::ztiles, \
+                        Geometry<R, NN>::zept};
     MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(48) MF_SHAPE(64) MF_SHAPE(80) MF_SHAPE(96)
     MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
 #undef MF_SHAPE
@@ -121,7 +124,7 @@ Layout make_layout(const mf_chain_desc& d) {
   L.status = take(nc * 4);
   L.partials = take(2 * nc * static_cast<size_t>(L.n_wg_max) * nb * 8);   // two sets (mixing)
   L.ratio = take(nc * nb * 8);
-  L.tobs = take(nc * static_cast<size_t>(sh.ztiles));
+  L.tobs = take(nc * static_cast<size_t>(sh.ztiles) * 4);
   L.coef = take(nc * 2 * m * rs);
   L.spec = take(nc * L.spec_stride * 2 * rs);
   L.staging = take(m * rs);
@@ -223,7 +226,7 @@ struct mf_problem {
   uint64_t sweep;
   WienerRun wiener;
   DiagRec diag;
-  std::vector<int> obs_tiles;   // per chain: z-pass tiles holding an observed voxel
+  std::vector<int> obs_chunks;  // per chain: z-pass (tile, element) chunks holding an observed voxel
   int xpath;                    // XPath of Gibbs sweeps
   int n_wg(int path) const { return path == kPathSplit ? L.n_wg_split : L.n_wg_whole; }
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
@@ -238,7 +241,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p, int path = -1) {
   char* ws = p->ws;
   a.spec = reinterpret_cast<mf::cx<R>*>(ws + p->L.spec);
   a.coef = reinterpret_cast<const R*>(ws + p->L.coef);
-  a.tile_obs = reinterpret_cast<const uint8_t*>(ws + p->L.tobs);
+  a.tile_obs = reinterpret_cast<const uint32_t*>(ws + p->L.tobs);
   a.ztiles = p->sh.ztiles;
   a.staging = reinterpret_cast<R*>(ws + p->L.staging);
   a.tau = reinterpret_cast<const double*>(ws + p->L.tau);
@@ -455,7 +458,7 @@ bool observed(const double* noise_var, const double* response, size_t i) {
 // arithmetic where N / R^2 is smallest (tau is that minimum); rounding of
 // tau R^2 / N there can leave -1 ulp, which is set back to 0.
 template <typename R, int N>
-void permute_coef(std::vector<R>& out, std::vector<uint8_t>& obs, const double* data,
+void permute_coef(std::vector<R>& out, std::vector<uint32_t>& obs, const double* data,
                   const double* noise_var, const double* response, double tau) {
   using T = mf::ZTile<R, N>;
   const int tiles = (N / T::IXB) * (N / T::P);
@@ -480,7 +483,8 @@ void permute_coef(std::vector<R>& out, std::vector<uint8_t>& obs, const double* 
         o[1] = static_cast<R>(alpha(vb));
         o[2] = static_cast<R>(beta(va));
         o[3] = static_cast<R>(beta(vb));
-        if (observed(noise_var, response, va) || observed(noise_var, response, vb)) obs[tile] = 1;
+        if (observed(noise_var, response, va) || observed(noise_var, response, vb))
+          obs[tile] |= 1u << e;
       }
 }
 
@@ -488,7 +492,7 @@ template <typename R>
 mf_status upload_coef(mf_problem* p, int c, const double* data, const double* noise_var,
                       const double* response, double tau, hipStream_t st) {
   std::vector<R> buf;
-  std::vector<uint8_t> obs;
+  std::vector<uint32_t> obs;
   switch (p->desc.n) {
 #define MF_PERMUTE(NN) \
   case NN: permute_coef<R, NN>(buf, obs, data, noise_var, response, tau); break;
@@ -498,10 +502,12 @@ mf_status upload_coef(mf_problem* p, int c, const double* data, const double* no
   }
   MF_HIP(hipMemcpyAsync(p->ws + p->L.coef + static_cast<size_t>(c) * buf.size() * sizeof(R),
                         buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st));
-  MF_HIP(hipMemcpyAsync(p->ws + p->L.tobs + static_cast<size_t>(c) * obs.size(), obs.data(),
-                        obs.size(), hipMemcpyHostToDevice, st));
-  if (p->obs_tiles.size() < static_cast<size_t>(p->desc.n_chains)) p->obs_tiles.resize(p->desc.n_chains);
-  p->obs_tiles[c] = static_cast<int>(std::count(obs.begin(), obs.end(), uint8_t{1}));
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.tobs + static_cast<size_t>(c) * obs.size() * 4, obs.data(),
+                        obs.size() * 4, hipMemcpyHostToDevice, st));
+  if (p->obs_chunks.size() < static_cast<size_t>(p->desc.n_chains)) p->obs_chunks.resize(p->desc.n_chains);
+  int chunks = 0;
+  for (uint32_t m : obs) chunks += __builtin_popcount(m);
+  p->obs_chunks[c] = chunks;
   MF_HIP(hipStreamSynchronize(st));
   return MF_OK;
 }
@@ -928,7 +934,7 @@ mf_status mf_sweep_bytes(const mf_problem* p, size_t* bytes) {
   const size_t part = static_cast<size_t>(p->n_wg(p->xpath)) * nb * 8;
   for (int k = 0; k < MF_NUM_KERNELS; ++k) bytes[k] = 0;
   for (int c = 0; c < p->desc.n_chains; ++c) {
-    const size_t coef = 2 * m * rs * static_cast<size_t>(p->obs_tiles[c]) / p->sh.ztiles;
+    const size_t coef = 2 * m * rs * static_cast<size_t>(p->obs_chunks[c]) / (p->sh.ztiles * p->sh.zept);
     bytes[0] += 2 * spec + coef;
     bytes[1] += 2 * spec;
     bytes[2] += 2 * spec + part;
@@ -1157,7 +1163,7 @@ mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, const R* coef, R* tabl
   a.gacc = gacc;
   a.tau = reinterpret_cast<const double*>(p->ws + p->L.tau) + c0;
   a.status = reinterpret_cast<uint32_t*>(p->ws + p->L.status) + c0;
-  a.tile_obs = reinterpret_cast<const uint8_t*>(p->ws + p->L.tobs) + static_cast<size_t>(c0) * p->sh.ztiles;
+  a.tile_obs = reinterpret_cast<const uint32_t*>(p->ws + p->L.tobs) + static_cast<size_t>(c0) * p->sh.ztiles;
   a.chain0 = p->desc.chain_id + c0;
   a.advance = 0;
   a.staging_chain = 0;

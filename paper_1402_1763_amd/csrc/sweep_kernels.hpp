@@ -39,7 +39,7 @@ template <typename R>
 struct SweepArgs {
   cx<R>* spec;            // chain c at spec + c * spec_stride
   const R* coef;          // chain c at coef + c * 2 m (z-pass thread order)
-  const uint8_t* tile_obs;  // [chain][z tile] 0 when every voxel of the tile is unobserved
+  const uint32_t* tile_obs;  // [chain][z tile] bit e: element e of the tile holds an observed voxel
   int32_t ztiles;         // z-pass tiles per chain
   R* staging;             // M reals, shared by all chains (state in/out)
   const double* tau;      // [chain]
@@ -122,6 +122,7 @@ struct ZTile {
   static constexpr int NT = NPEN * N / EPT;
   static constexpr int PSTR = N + 1;
   using TL = Tile<N, NPEN, NT, true, PSTR, 0>;
+  static_assert(EPT <= 32, "one observation bit per element");
   // FP64 at N = 256 would take 256 VGPRs and 8 AGPRs (1 wave per SIMD); held
   // to 256 registers (2 waves, no spill) the FP64 sweep runs 8% faster.
   static constexpr int MIN_WAVES = (sizeof(R) == 8 && N == 256) ? 2 : 1;
@@ -206,14 +207,16 @@ __host__ __device__ inline void zpass_coef_voxel(int tile, int e, int tid, int& 
   iya = (tile % (N / T::P)) * T::P + 2 * (pen % T::NPAIR);
 }
 
-// Whether z-pass tile `tile` of chain c holds an observed voxel.  Tiles with
-// none skip their coefficient loads: alpha = 1 and beta = 0 there exactly.
-// The flag is the same for the whole workgroup.
+// Which elements of z-pass tile `tile` of chain c hold an observed voxel:
+// bit e covers element e of every lane (at N = 256, the z range
+// [16 e, 16 e + 16) of the tile's pencils).  Elements with none skip their
+// coefficient loads: alpha = 1 and beta = 0 there exactly.  The mask is the
+// same for the whole workgroup.
 template <typename R>
-__device__ __forceinline__ bool tile_observed(const SweepArgs<R>& a, int c, int tile) {
-  if (a.tile_obs == nullptr) return true;
-  const int f = a.tile_obs[static_cast<size_t>(c) * a.ztiles + tile];
-  return __builtin_amdgcn_readfirstlane(f) != 0;
+__device__ __forceinline__ uint32_t tile_obs_mask(const SweepArgs<R>& a, int c, int tile) {
+  if (a.tile_obs == nullptr) return ~0u;
+  const uint32_t f = a.tile_obs[static_cast<size_t>(c) * a.ztiles + tile];
+  return __builtin_amdgcn_readfirstlane(f);
 }
 
 // Workgroup = IXB consecutive ix and P consecutive iy; z pencils (iy, iy + 1)
@@ -337,12 +340,12 @@ zpass_kernel(SweepArgs<R> a) {
   } else if (MODE == kZDet) {
     const int tile = blockIdx.y * (N / T::P) + blk;
     const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m + static_cast<size_t>(tile) * EPT * NT * 4;
-    const bool obs = tile_observed(a, c, tile);
+    const uint32_t obs = tile_obs_mask(a, c, tile);
     const R cb = a.cb_over_tau ? static_cast<R>(static_cast<double>(a.cb) / a.tau[c]) : a.cb;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       R cf[4] = {R(1), R(1), R(0), R(0)};
-      if (obs) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
+      if ((obs >> e) & 1u) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
       const cx<R> s = v[e];
       v[e] = cx<R>{a.cs * cf[0] * s.x + cb * cf[2], a.cs * cf[1] * s.y + cb * cf[3]};
     }
@@ -350,7 +353,7 @@ zpass_kernel(SweepArgs<R> a) {
     const R tau = static_cast<R>(a.tau[c]);
     const int tile = blockIdx.y * (N / T::P) + blk;
     const R* coef = a.coef + static_cast<size_t>(c) * 2 * a.m + static_cast<size_t>(tile) * EPT * NT * 4;
-    const bool obs = tile_observed(a, c, tile);
+    const uint32_t obs = tile_obs_mask(a, c, tile);
     const uint32_t chain = a.chain0 + c;
 #pragma unroll
     for (int i = 0; i < EPT / RL; ++i) {
@@ -377,7 +380,7 @@ zpass_kernel(SweepArgs<R> a) {
         for (int j = 0; j < 4; ++j) {
           const int e = i * RL + cq + j * (RL / 4);
           R cf[4] = {R(1), R(1), R(0), R(0)};
-          if (obs) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
+          if ((obs >> e) & 1u) ld4(coef + (static_cast<size_t>(e) * NT + tid) * 4, cf);
           const cx<R> s = v[e];
           const R ta = cf[0] * s.x + cf[2] + noise_amp(tau * cf[0]) * ga[j];
           const R tb = cf[1] * s.y + cf[3] + noise_amp(tau * cf[1]) * gb[j];
