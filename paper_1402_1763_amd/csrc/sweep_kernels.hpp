@@ -363,16 +363,19 @@ zpass_kernel(SweepArgs<R> a) {
       const uint32_t wa = static_cast<uint32_t>((ix * N + iya) * (N / 4) + q);
 #pragma unroll
       for (int cq = 0; cq < RL / 4; ++cq) {
+        // three-input XORs in Philox at 256^3 FP32 only (0.4 us there);
+        // elsewhere the extra registers cross an occupancy step
+        constexpr bool kXor3 = sizeof(R) == 4 && N == 256;
         R ga[4], gb[4];
         {
-          const Words4 w = philox4x32_10(wa + NSL * cq, sweep, kPhaseMessenger, chain,
-                                         a.key0, a.key1);
+          const Words4 w = philox4x32_10<kXor3>(wa + NSL * cq, sweep, kPhaseMessenger, chain,
+                                                a.key0, a.key1);
           box_muller(w.x0, w.x1, ga[0], ga[1]);
           box_muller(w.x2, w.x3, ga[2], ga[3]);
         }
         {
-          const Words4 w = philox4x32_10(wa + N / 4 + NSL * cq, sweep, kPhaseMessenger,
-                                         chain, a.key0, a.key1);
+          const Words4 w = philox4x32_10<kXor3>(wa + N / 4 + NSL * cq, sweep, kPhaseMessenger,
+                                                chain, a.key0, a.key1);
           box_muller(w.x0, w.x1, gb[0], gb[1]);
           box_muller(w.x2, w.x3, gb[2], gb[3]);
         }
