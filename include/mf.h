@@ -199,8 +199,9 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, i
  * sweep order), summed over the problem's chains.  Each pass reads and
  * writes the half-complex field once, 2 (N/2 + 1) N^2 reals each way.  On
  * top of that:
- *  - the z-pass reads the two messenger coefficients of every voxel in its
- *    tiles that hold an observed voxel (tiles with none skip the read);
+ *  - the z-pass reads the two messenger coefficients of every voxel in the
+ *    chunks of its tiles that hold an observed voxel (a chunk is one element
+ *    of every lane of a tile; chunks with none skip the read);
  *  - the x-pass writes one FP64 shell partial per bin and workgroup;
  *  - the inverse y-pass reads those partials and updates P and its table.
  * These are the per-unit figures behind the roofline of each kernel. */
