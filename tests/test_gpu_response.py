@@ -108,3 +108,37 @@ def test_wiener_gradient_with_response_matches_oracle(precision):
         assert e_s < tol and e_c < tol and e_gd < tol and e_gp < tol
         assert np.all(grad_d[c].cpu().numpy()[~prob.observed] == 0.0)
     smp.close()
+
+
+def test_response_in_fp32_mixing_and_in_a_graph():
+    """FP32 mixing sweeps with a response against the oracle (the MH decisions
+    are taken in FP64 from FP32 fields, so this also checks none flips here),
+    and graph replays of a response problem against eager sweeps, bitwise."""
+    w, pb, rs, ds = _response_problem(48, 8, "fp32", 47)
+    smp = binding.Sampler(ds[0], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                          seed=w.rng_seed, precision="fp32", response=rs[0])
+    smp.sweep(3)
+    smp.mixing_sweep(2)
+    s_gpu, p_gpu, _ = smp.state()
+    smp.close()
+    prob = _oracle(w, pb, ds[0], rs[0])
+    st = sampler.run_chain(prob, sampler.State(s=np.zeros((48,) * 3),
+                                               p_grid=pb["pk_init"] / w.cell_volume), 3)
+    st = mixing.mixing_sweep(prob, mixing.mixing_sweep(prob, st))
+    err_s, err_p = errors(s_gpu, p_gpu, st.s, st.p_grid * w.cell_volume)
+    print(f"response mixing fp32 err_s={err_s:.2e} err_P={err_p:.2e}", flush=True)
+    assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
+
+    a = binding.Sampler(ds[0], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                        seed=w.rng_seed, precision="fp32", response=rs[0])
+    b = binding.Sampler(ds[0], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                        seed=w.rng_seed, precision="fp32", response=rs[0])
+    a.sweep(5)
+    g = binding.SweepGraph([b])
+    g.launch(5)
+    g.close()
+    sa, pa, na = a.state()
+    sb, pb_, nb_ = b.state()
+    a.close()
+    b.close()
+    assert na == nb_ == 5 and np.array_equal(sa, sb) and np.array_equal(pa, pb_)
