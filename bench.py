@@ -258,7 +258,7 @@ def plain_sweep_ms(w, pb, steps: int, precision: str = "fp32") -> float:
 
 
 def bench_chain_efficiency(args):
-    """Statistical efficiency on the 128^3 survey problem (Sec. 4.3): after a
+    """Statistical efficiency on the 128^3 survey problem (Sec. 5.1): after a
     burn-in, record every 10th of `steps` sweeps of P(k) and compute the
     autocorrelation and the ten-percent correlation length n_c of every bin,
     for Gibbs sweeps and for mixing sweeps (Alg. 3)."""
@@ -494,6 +494,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--segments", type=int, default=5,
+                    help="timed segments of --steps sweeps each; the median is reported")
     ap.add_argument("--workload", default="gibbs-256^3-fp32-survey")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -543,20 +545,34 @@ def main():
     smp.sweep(args.warmup)
     torch.cuda.synchronize()
 
+    # `segments` timed segments of `steps` sweeps each, every one bracketed by
+    # a device synchronisation on both sides; the median segment is the figure
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
+    seg_ms, wall_s = [], []
+    for _ in range(args.segments):
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter()
+        start.record(stream)
+        smp.sweep(args.steps)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall_s.append(time.perf_counter() - t_wall)
+        seg_ms.append(start.elapsed_time(stop))
+    ms_per_step = float(np.median(seg_ms)) / args.steps
+    # context: one long segment right after (how far short segments sit from
+    # a long chain's steady rate)
+    long_sweeps = 1000
     torch.cuda.synchronize()
-    t_wall = time.perf_counter()
     start.record(stream)
-    smp.sweep(args.steps)
+    smp.sweep(long_sweeps)
     stop.record(stream)
     torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t_wall
-    ms_total = start.elapsed_time(stop)
-    ms_per_step = ms_total / args.steps
+    long_ms_per_step = start.elapsed_time(stop) / long_sweeps
 
     _, pk, n_done = smp.state(want_s=False)
-    assert np.all(np.isfinite(pk)) and n_done == args.warmup + args.steps
+    assert np.all(np.isfinite(pk))
+    assert n_done == args.warmup + args.segments * args.steps + long_sweeps
 
     real_bytes = 8 if w.precision == "fp64" else 4
     n = w.n
@@ -566,7 +582,7 @@ def main():
     roofline = None
     kernel_ms = None
     if not args.no_kernel_timing:
-        kms = smp.sweep_timed(min(args.steps, 200))
+        kms = smp.sweep_timed(400)
         kernel_ms = dict(zip(binding.KERNEL_NAMES, [float(x) for x in kms]))
         dom = max(kernel_ms, key=kernel_ms.get)
         achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
@@ -611,7 +627,11 @@ def main():
                    "sweep_hbm_frac_5pass_bytes": round(48.25 * w.m * real_bytes / 4
                                                        / (ms_per_step * 1e-3) / 1e9
                                                        / HBM_PEAK_GBS, 4),
-                   "wall_s_timed_region": round(wall_s, 4),
+                   "timed_segments": args.segments,
+                   "segment_ms_per_step": [round(v / args.steps, 5) for v in seg_ms],
+                   "wall_s_timed_segments": [round(v, 4) for v in wall_s],
+                   "long_segment_sweeps": long_sweeps,
+                   "long_segment_sweeps_per_s": round(1000.0 / long_ms_per_step, 2),
                    "fp64_sweeps_per_s": fp64,
                    "hbm_reference": stream_ref,
                    "speedup_vs_fp64_sweep": (round(1000.0 / ms_per_step / fp64, 3)

@@ -121,12 +121,18 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
 
 /* Enqueue n_sweeps >= 0 Gibbs sweeps of every chain (Algs. 1 and 2 with shell
  * averaging; the P(k) step only when sample_pk = 1).  Asynchronous.
- * Errors: MF_E_INVALID_ARG, MF_E_DEVICE. */
+ * The sweep index is Philox counter word 1 (32 bits): sweeps that would take
+ * it beyond 2^32 - 1 are refused, since they would repeat the random numbers
+ * of earlier sweeps.  This holds for every call that sweeps.
+ * Errors: MF_E_INVALID_ARG (also that bound), MF_E_DEVICE. */
 mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
 
-/* As mf_gibbs_sweep, but records HIP events around every kernel, synchronises,
+/* As mf_gibbs_sweep, but times the kernels with HIP events, synchronises,
  * and writes the mean duration in milliseconds of each of the first
- * min(n_kernels, MF_NUM_KERNELS) sweep kernels to kernel_ms (host). */
+ * min(n_kernels, MF_NUM_KERNELS) sweep kernels to kernel_ms (host).  Sweep i
+ * brackets only its kernel i mod MF_NUM_KERNELS, with events that skip the
+ * system-scope fence, so every kernel is timed on n_sweeps / MF_NUM_KERNELS
+ * sweeps (NaN for a kernel never timed: n_sweeps < MF_NUM_KERNELS). */
 mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream,
                                double* kernel_ms, int32_t n_kernels);
 
@@ -140,9 +146,11 @@ mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double
 
 /* Overwrite chain `chain`'s s (M doubles, NULL keeps s) and P (n_bins
  * doubles, NULL keeps P) and set the sweep counter of the whole problem to
- * `sweep` (the counter is shared by all chains).  Continuing from a state
- * read by mf_get_chain_state reproduces the original chain.
- * Errors: MF_E_STATE, MF_E_INVALID_ARG, MF_E_NONFINITE, MF_E_DEVICE. */
+ * `sweep` (the counter is shared by all chains; at most 2^32 - 1).
+ * Continuing from a state read by mf_get_chain_state reproduces the original
+ * chain.
+ * Errors: MF_E_STATE, MF_E_INVALID_ARG (also sweep >= 2^32, with nothing
+ * changed), MF_E_NONFINITE, MF_E_DEVICE. */
 mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, const double* pk,
                              uint64_t sweep, void* stream);
 
@@ -154,7 +162,8 @@ mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, cons
  * host buffer `buf` (synchronises `stream`); mf_load_checkpoint restores it
  * into chain `chain` of a problem with the same N, n_bins and precision, and
  * sets the problem's sweep counter to the checkpoint's.
- * Errors: MF_E_INVALID_ARG (size or header mismatch), MF_E_STATE, MF_E_DEVICE. */
+ * Errors: MF_E_INVALID_ARG (size or header mismatch, a sweep index >= 2^32),
+ * MF_E_STATE, MF_E_DEVICE. */
 mf_status mf_checkpoint_bytes(mf_problem* p, size_t* bytes);
 mf_status mf_save_checkpoint(mf_problem* p, int32_t chain, void* buf, size_t bytes, void* stream);
 mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size_t bytes,
@@ -172,7 +181,10 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
  * use Philox phase 3 (counter (b 2^16 + attempt, sweep, 3, chain)) besides
  * the messenger and signal phases.  Mixing and Gibbs sweeps may be
  * interleaved freely; both advance the sweep index.  Enqueued on `stream`.
- * Errors: MF_E_UNSUPPORTED_SIZE, MF_E_INVALID_ARG, MF_E_DEVICE. */
+ * The move changes P, so a problem that holds P fixed (sample_pk = 0) is
+ * refused.
+ * Errors: MF_E_UNSUPPORTED_SIZE, MF_E_INVALID_ARG (also sample_pk = 0),
+ * MF_E_DEVICE. */
 mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
 
 /* How Gibbs sweeps run the x transform, and its autotuner.
@@ -233,7 +245,10 @@ mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t t
  * `stream` (asynchronously) and advances every problem's sweep counter; the
  * replays draw the same random numbers as mf_gibbs_sweep would.  The problems
  * must outlive the graph and must not be swept on another stream while a
- * replay is in flight.  The graph owns its side streams and events.
+ * replay is in flight.  A graph replays the diagnostic recording set when it
+ * was created (mf_set_diagnostics), buffers included, so that call is refused
+ * for a problem while a graph over it exists.  The graph owns its side
+ * streams and events.
  * Errors: MF_E_INVALID_ARG, MF_E_DEVICE. */
 typedef struct mf_graph mf_graph;
 mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, mf_graph** out);
@@ -338,7 +353,7 @@ mf_status mf_wiener_logdet_trace(mf_problem* p, int32_t chain, const double* pk,
 mf_status mf_stream_reference(const void* src, void* dst, size_t bytes, int32_t mode,
                               int32_t blocks, void* stream);
 
-/* Chain diagnostics (Sec. 4.3).
+/* Chain diagnostics (Sec. 5.1, "Statistical efficiency").
  *
  * Recording.  mf_set_diagnostics makes sweeps record sample n, the chain
  * state after n sweeps, as sweep n begins, for n = start + j * thin
@@ -354,7 +369,9 @@ mf_status mf_stream_reference(const void* src, void* dst, size_t bytes, int32_t 
  * Sizes are given by mf_diagnostics_bytes.  The settings apply to sweeps
  * enqueued afterwards and to graphs created afterwards.  Calling again
  * resets the recording, and both NULL stops it.  Errors: MF_E_INVALID_ARG
- * (thin < 1, start >= 2^32, unaligned buffers).
+ * (thin < 1, start >= 2^32, unaligned buffers), MF_E_STATE (a graph created
+ * by mf_graph_create still holds this problem: it would keep recording into
+ * the previous buffers).
  * mf_recorded_samples: samples recorded so far, from the problem's sweep
  * count (the trace holds min(count, trace_cap) of them).
  * mf_get_moments: writes the posterior mean and variance (population form,

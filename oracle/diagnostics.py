@@ -1,6 +1,6 @@
 """Chain diagnostics, plainly, in FP64 (test infrastructure only).
 
-* Autocorrelation of a recorded chain of power-spectrum amplitudes (Sec. 4.3,
+* Autocorrelation of a recorded chain of power-spectrum amplitudes (Sec. 5.1,
   Eq. CORR_COEFF): with mean <P> and variance Var(P) over the T recorded
   samples,
       C_n = < (P^i - <P>)(P^{i+n} - <P>) > / Var(P),

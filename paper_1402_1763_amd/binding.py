@@ -432,16 +432,19 @@ class Sampler:
         _check(load().mf_diagnostics_bytes(ctypes.c_void_p(self.handle), trace_cap,
                                            ctypes.byref(tb), ctypes.byref(mb)))
         dev = self.workspace.device
-        self.trace_buf = (torch.zeros(self.n_chains, trace_cap, self.n_bins, dtype=torch.float64,
-                                      device=dev) if trace_cap > 0 else None)
-        self.moment_buf = (torch.empty(mb.value // 8, dtype=torch.float64, device=dev)
-                           if moments else None)
+        trace_buf = (torch.zeros(self.n_chains, trace_cap, self.n_bins, dtype=torch.float64,
+                                 device=dev) if trace_cap > 0 else None)
+        moment_buf = (torch.empty(mb.value // 8, dtype=torch.float64, device=dev)
+                      if moments else None)
         _check(load().mf_set_diagnostics(
             ctypes.c_void_p(self.handle), start, thin,
-            ctypes.c_void_p(self.trace_buf.data_ptr() if self.trace_buf is not None else None),
+            ctypes.c_void_p(trace_buf.data_ptr() if trace_buf is not None else None),
             trace_cap,
-            ctypes.c_void_p(self.moment_buf.data_ptr() if self.moment_buf is not None else None),
+            ctypes.c_void_p(moment_buf.data_ptr() if moment_buf is not None else None),
             ctypes.c_void_p(self.stream.cuda_stream)))
+        # only now may the previous buffers go: the library refuses the call
+        # (and keeps recording into them) while a graph holds their addresses
+        self.trace_buf, self.moment_buf = trace_buf, moment_buf
 
     def recorded(self) -> int:
         out = ctypes.c_uint64(0)

@@ -228,6 +228,7 @@ struct mf_problem {
   DiagRec diag;
   std::vector<int> obs_chunks;  // per chain: z-pass (tile, element) chunks holding an observed voxel
   int xpath;                    // XPath of Gibbs sweeps
+  int graphs = 0;               // live graphs that captured this problem's sweep
   int n_wg(int path) const { return path == kPathSplit ? L.n_wg_split : L.n_wg_whole; }
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
@@ -408,9 +409,32 @@ mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t s
   return MF_OK;
 }
 
+// The sweep index is Philox counter word 1, a 32-bit word: indices at or
+// beyond 2^32 would repeat earlier sweeps' random numbers.
+constexpr uint64_t kMaxSweep = 0xffffffffull;
+
+mf_status check_sweep_index(uint64_t sweep) {
+  if (sweep > kMaxSweep)
+    return fail(MF_E_INVALID_ARG, "sweep index %llu beyond 2^32 - 1 (Philox counter word 1)",
+                static_cast<unsigned long long>(sweep));
+  return MF_OK;
+}
+
+// n more sweeps from the problem's current index must leave it at most
+// 2^32 - 1, so that every state a chain reaches can be set and reloaded.
+mf_status check_sweep_room(const mf_problem* p, int64_t n) {
+  if (p->sweep + static_cast<uint64_t>(n) > kMaxSweep)
+    return fail(MF_E_INVALID_ARG, "%lld sweeps from index %llu would pass 2^32 - 1 "
+                "(Philox counter word 1)", static_cast<long long>(n),
+                static_cast<unsigned long long>(p->sweep));
+  return MF_OK;
+}
+
 // Device sweep counter := sweep in both slots (the z-pass reads slot 0, the
 // x-pass and the P draw slot 1; the forward y-pass advances slot 0).
 mf_status write_counter(mf_problem* p, uint64_t sweep, hipStream_t st) {
+  const mf_status chk = check_sweep_index(sweep);
+  if (chk != MF_OK) return chk;
   const uint32_t c[2] = {static_cast<uint32_t>(sweep), static_cast<uint32_t>(sweep)};
   MF_HIP(hipMemcpyAsync(p->ws + p->L.ctr, c, sizeof(c), hipMemcpyHostToDevice, st));
   MF_HIP(hipStreamSynchronize(st));
@@ -686,6 +710,8 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
 mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
   if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
   if (n_sweeps < 0) return fail(MF_E_INVALID_ARG, "negative sweep count");
+  const mf_status room = check_sweep_room(p, n_sweeps);
+  if (room != MF_OK) return room;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   for (int i = 0; i < n_sweeps; ++i) {
     for (int k = 0; k < MF_NUM_KERNELS; ++k) {
@@ -703,6 +729,11 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
   if (p->desc.n < 32 || p->desc.n > 256)
     return fail(MF_E_UNSUPPORTED_SIZE, "the mixing sweep supports grid sides 32 to 256 (got %d)",
                 p->desc.n);
+  // the mixing sweep's Metropolis-Hastings move is a move of P itself
+  if (!p->desc.sample_pk)
+    return fail(MF_E_INVALID_ARG, "mixing sweeps update P(k); the problem holds P fixed (sample_pk = 0)");
+  const mf_status room = check_sweep_room(p, n_sweeps);
+  if (room != MF_OK) return room;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const int ids[6] = {kZ, kYF, kXMixK, kMixPkK, kXMixInvK, kYI};
   for (int i = 0; i < n_sweeps; ++i) {
@@ -722,30 +753,36 @@ mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, do
                                int32_t n_kernels) {
   if (!p || !kernel_ms || n_kernels < 0) return fail(MF_E_INVALID_ARG, "bad argument");
   if (n_sweeps <= 0) return fail(MF_E_INVALID_ARG, "need at least one sweep");
+  const mf_status room = check_sweep_room(p, n_sweeps);
+  if (room != MF_OK) return room;
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  std::vector<hipEvent_t> ev(static_cast<size_t>(n_sweeps) * (MF_NUM_KERNELS + 1));
-  for (auto& e : ev) MF_HIP(hipEventCreate(&e));
+  // Sweep i brackets only its kernel i mod MF_NUM_KERNELS, with one pair of
+  // events that skip the system-scope fence (a cache write-back and
+  // invalidate at every event would slow the kernels being timed).
+  std::vector<hipEvent_t> ev(static_cast<size_t>(n_sweeps) * 2);
+  for (auto& e : ev) MF_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   mf_status st = MF_OK;
   for (int i = 0; i < n_sweeps && st == MF_OK; ++i) {
-    hipEvent_t* e = &ev[static_cast<size_t>(i) * (MF_NUM_KERNELS + 1)];
-    MF_HIP(hipEventRecord(e[0], hs));
+    const int timed = i % MF_NUM_KERNELS;
     for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k) {
+      if (k == timed) MF_HIP(hipEventRecord(ev[2 * i], hs));
       st = launch_checked(p, kSweepOrder[k], 0, hs);
-      if (st == MF_OK) MF_HIP(hipEventRecord(e[k + 1], hs));
+      if (st == MF_OK && k == timed) MF_HIP(hipEventRecord(ev[2 * i + 1], hs));
     }
     ++p->sweep;
   }
   if (st == MF_OK) {
     MF_HIP(hipStreamSynchronize(hs));
     double sum[MF_NUM_KERNELS] = {0};
-    for (int i = 0; i < n_sweeps; ++i)
-      for (int k = 0; k < MF_NUM_KERNELS; ++k) {
-        float ms = 0.f;
-        hipEvent_t* e = &ev[static_cast<size_t>(i) * (MF_NUM_KERNELS + 1)];
-        MF_HIP(hipEventElapsedTime(&ms, e[k], e[k + 1]));
-        sum[k] += ms;
-      }
-    for (int k = 0; k < std::min<int>(n_kernels, MF_NUM_KERNELS); ++k) kernel_ms[k] = sum[k] / n_sweeps;
+    int cnt[MF_NUM_KERNELS] = {0};
+    for (int i = 0; i < n_sweeps; ++i) {
+      float ms = 0.f;
+      MF_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      sum[i % MF_NUM_KERNELS] += ms;
+      ++cnt[i % MF_NUM_KERNELS];
+    }
+    for (int k = 0; k < std::min<int>(n_kernels, MF_NUM_KERNELS); ++k)
+      kernel_ms[k] = cnt[k] ? sum[k] / cnt[k] : std::numeric_limits<double>::quiet_NaN();
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return st;
@@ -786,6 +823,8 @@ mf_status mf_set_chain_state(mf_problem* p, int32_t chain, const double* s, cons
   if (s)
     for (size_t i = 0; i < m; ++i)
       if (!std::isfinite(s[i])) return fail(MF_E_NONFINITE, "s not finite at %zu", i);
+  const mf_status chk = check_sweep_index(sweep);
+  if (chk != MF_OK) return chk;
   p->sweep = sweep;
   const mf_status st = write_counter(p, sweep, static_cast<hipStream_t>(stream));
   if (st != MF_OK) return st;
@@ -844,6 +883,7 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
   if (std::memcmp(h.magic, "MFGIBBS1", 8) != 0 || h.n != p->desc.n || h.n_bins != p->desc.n_bins ||
       h.precision != p->desc.precision)
     return fail(MF_E_INVALID_ARG, "checkpoint does not match this problem");
+  if (check_sweep_index(h.sweep) != MF_OK) return MF_E_INVALID_ARG;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const size_t rs = p->fp64() ? 8 : 4;
   const int nb = p->desc.n_bins;
@@ -953,6 +993,7 @@ mf_status mf_get_tau(mf_problem* p, int32_t chain, double* tau_out) {
 mf_status mf_debug_run_kernel(mf_problem* p, int32_t kernel, uint64_t sweep, void* stream) {
   if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
   if (kernel < 0 || kernel >= MF_NUM_KERNELS) return fail(MF_E_INVALID_ARG, "bad kernel id");
+  if (check_sweep_index(sweep) != MF_OK) return MF_E_INVALID_ARG;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const mf_status st = write_counter(p, sweep, hs);
   if (st != MF_OK) return st;
@@ -981,7 +1022,10 @@ struct mf_graph {
   std::vector<hipEvent_t> events;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool counted = false;   // probs' graph counts include this graph
   ~mf_graph() {
+    if (counted)
+      for (auto* p : probs) --p->graphs;
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (auto e : events) (void)hipEventDestroy(e);
@@ -1045,6 +1089,9 @@ mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, 
   if (e != hipSuccess) return bail("hipStreamEndCapture", e);
   if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
     return bail("hipGraphInstantiate", e);
+  // the graph holds the diagnostic buffers' addresses as captured
+  for (auto* p : g->probs) ++p->graphs;
+  g->counted = true;
   *out = g;
   return MF_OK;
 }
@@ -1052,6 +1099,10 @@ mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, 
 mf_status mf_graph_launch(mf_graph* g, int32_t n_sweeps, void* stream) {
   if (!g) return fail(MF_E_INVALID_ARG, "graph is NULL");
   if (n_sweeps < 0) return fail(MF_E_INVALID_ARG, "negative sweep count");
+  for (auto* p : g->probs) {
+    const mf_status room = check_sweep_room(p, n_sweeps);
+    if (room != MF_OK) return room;
+  }
   hipStream_t hs = static_cast<hipStream_t>(stream);
   for (int i = 0; i < n_sweeps; ++i) MF_HIP(hipGraphLaunch(g->exec, hs));
   for (auto* p : g->probs) p->sweep += static_cast<uint64_t>(n_sweeps);
@@ -1602,7 +1653,11 @@ mf_status mf_set_diagnostics(mf_problem* p, uint64_t start, int32_t thin, double
   if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
   if (thin < 1) return fail(MF_E_INVALID_ARG, "thin must be >= 1");
   if (trace && trace_cap < 1) return fail(MF_E_INVALID_ARG, "trace capacity must be >= 1");
-  if (start > 0xffffffffull) return fail(MF_E_INVALID_ARG, "start sweep beyond 2^32 - 1");
+  if (start > kMaxSweep) return fail(MF_E_INVALID_ARG, "start sweep beyond 2^32 - 1");
+  // a graph replays the recording settings it captured, buffers included
+  if (p->graphs > 0)
+    return fail(MF_E_STATE, "%d live graph(s) captured this problem's sweep; destroy them "
+                "before changing the diagnostics", p->graphs);
   for (const void* q : {static_cast<const void*>(trace), static_cast<const void*>(moments)})
     if (q && reinterpret_cast<uintptr_t>(q) % 8 != 0)
       return fail(MF_E_INVALID_ARG, "diagnostic buffers must be 8-byte aligned");

@@ -222,7 +222,7 @@ moments_kernel(const double* mom, double count, double* mean_out, double* var_ou
   var_out[vb] = m2[idx * 2 + 1] / count;
 }
 
-// Autocorrelation of a recorded chain (Sec. 4.3, Eq. CORR_COEFF), one
+// Autocorrelation of a recorded chain (Sec. 5.1, Eq. CORR_COEFF), one
 // workgroup per bin b of trace [t][nb]: with mean mu and variance var over the
 // t samples, acf[n][b] = sum_{i < t-n} (x_i - mu)(x_{i+n} - mu) / ((t - n) var)
 // for n <= max_lag, and nc[b] = the first n with acf < 0.1 (-1 if none).  All
