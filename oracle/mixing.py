@@ -37,10 +37,18 @@ One mixing sweep:
   t ~ messenger conditional;  t^ = DFT(t);  s^ ~ signal conditional at P;
   per bin: the MH move of S^_b;  s^_k *= sqrt(S^'_b / S^_b);  s = DFT^-1 s^.
 
+With the optional conjugate prior InvGamma(a0, b0) on P_b (density
+~ P^-(a0+1) exp(-b0/P)) in place of Jeffreys', the prior of U = sqrt(S^)
+becomes ~ U^-(2 a0 + 1) exp(-M b0 / U^2) (b0 in grid units), and the
+acceptance probability min(1, (U/U')^(2 a0 + 1) exp(M b0 (1/U^2 - 1/U'^2))).
+At a0 = b0 = 0 this is Jeffreys' min(1, U/U'), which is evaluated as that
+ratio itself.
+
 Pins (tests/test_oracle_mixing.py): iterating the (x^, S^) update at fixed
 t^ leaves the exact conditional marginal of P invariant,
-p(P | t^) ~ P^-1 prod_k N(t^_k; 0, M (P + tau)), checked by quadrature on a
-small grid; the printed (U'/U)^2 acceptance fails the same check.
+p(P | t^) ~ prior(P) prod_k N(t^_k; 0, M (P + tau)), checked by quadrature
+on a small grid, with Jeffreys' prior and with a proper InvGamma prior; the
+printed (U'/U)^2 acceptance fails the same check.
 """
 from __future__ import annotations
 
@@ -87,6 +95,17 @@ def truncated_normal(mean: float, sd: float, seed: int, chain: int, sweep: int, 
     return None, u_mh
 
 
+def accept(u_mh: float, u: float, u_new: float, prob: sampler.Problem) -> bool:
+    """Metropolis-Hastings acceptance of U -> U' for the independence
+    proposal, under the problem's prior on P (grid units, S^ = M P = U^2)."""
+    a0, b0 = prob.prior_shape, prob.prior_scale_grid
+    if a0 == 0.0 and b0 == 0.0:
+        return u_mh <= u / u_new
+    log_ratio = (2.0 * a0 + 1.0) * np.log(u / u_new) + prob.m * b0 * (1.0 / (u * u)
+                                                                      - 1.0 / (u_new * u_new))
+    return np.log(u_mh) <= log_ratio
+
+
 def mix_power_step(s_hat, t_hat, p_grid, prob: sampler.Problem, sweep: int):
     """The MH move of every S^_b given t^ and the drawn s^ (at the current P).
 
@@ -106,7 +125,7 @@ def mix_power_step(s_hat, t_hat, p_grid, prob: sampler.Problem, sweep: int):
             continue
         u_new, u_mh = truncated_normal(xt[b] / xx[b], np.sqrt(t_cov / xx[b]), prob.seed,
                                        prob.chain, sweep, b)
-        if u_new is not None and u_mh <= root_s[b] / u_new:
+        if u_new is not None and accept(u_mh, root_s[b], u_new, prob):
             p_new[b] = u_new * u_new / m
             ratio[b] = u_new / root_s[b]
     return p_new, ratio

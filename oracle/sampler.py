@@ -31,7 +31,12 @@ sigma^t, mu^s, sigma^s and the inverse-gamma conditional):
      P_b ~ InvGamma(n_b / 2, sigma_b / (2 M)) in grid units (variance per
      voxel), drawn as P_b = sigma_b / (2 M g) with g ~ Gamma(n_b / 2, 1); for a
      single mode this is the paper's chi-square construction
-     S^ = |s^|^2 / G^2;
+     S^ = |s^|^2 / G^2.  Optionally the prior is the conjugate
+     InvGamma(a0, b0) (density ~ P^-(a0+1) exp(-b0/P), Jeffreys' at
+     a0 = b0 = 0): the conditional becomes InvGamma(n_b/2 + a0,
+     sigma_b/(2M) + b0), drawn as P_b = (sigma_b + 2 M b0) / (2 M g) with
+     g ~ Gamma(n_b/2 + a0, 1).  Jeffreys' prior leaves the joint posterior
+     improper as P_b -> 0 wherever the noise is finite; b0 > 0 removes that;
   6. s = inverse DFT of s^ (with the 1/M factor).
 The redundant forward transform of s in Alg. 1 is skipped: s^ is redrawn in
 full in step 3.  The draws come from the Philox contract in oracle.philox.
@@ -70,6 +75,8 @@ class Problem:
     seed: int
     chain: int = 0
     response: Optional[np.ndarray] = None   # (n, n, n) float64 R_i; None: R_i = 1
+    prior_shape: float = 0.0   # a0 of the InvGamma(a0, b0) prior on P_b (0, 0: Jeffreys)
+    prior_scale: float = 0.0   # b0, physical units (volume)
 
     @property
     def m(self) -> int:
@@ -78,6 +85,11 @@ class Problem:
     @property
     def cell_volume(self) -> float:
         return (self.box / self.n) ** 3
+
+    @property
+    def prior_scale_grid(self) -> float:
+        """b0 in grid units (variance per voxel), like P_grid."""
+        return self.prior_scale / self.cell_volume
 
     @property
     def observed(self) -> np.ndarray:
@@ -93,9 +105,14 @@ class Problem:
 
 
 def make_problem(data, noise_var, n_bins: int, box: float, seed: int, chain: int = 0,
-                 tau: Optional[float] = None, response=None) -> Problem:
+                 tau: Optional[float] = None, response=None, prior=(0.0, 0.0)) -> Problem:
     """tau defaults to the smallest observed N_i / R_i^2; a given tau must not
-    exceed it (the augmented noise N - R T R must stay positive)."""
+    exceed it (the augmented noise N - R T R must stay positive).  prior =
+    (a0, b0) of the InvGamma prior on every P_b, b0 in physical units; (0, 0)
+    is Jeffreys' prior."""
+    a0, b0 = (float(v) for v in prior)
+    if not (np.isfinite(a0) and np.isfinite(b0) and a0 >= 0.0 and b0 >= 0.0):
+        raise ValueError("prior (a0, b0) must be finite and >= 0")
     data = np.asarray(data, dtype=np.float64)
     noise_var = np.asarray(noise_var, dtype=np.float64)
     if response is not None:
@@ -104,7 +121,8 @@ def make_problem(data, noise_var, n_bins: int, box: float, seed: int, chain: int
             raise ValueError("response not finite")
     n = data.shape[0]
     prob = Problem(n=n, box=float(box), n_bins=int(n_bins), data=data, noise_var=noise_var,
-                   tau=0.0, seed=int(seed), chain=int(chain), response=response)
+                   tau=0.0, seed=int(seed), chain=int(chain), response=response,
+                   prior_shape=a0, prior_scale=b0)
     obs = prob.observed
     if not obs.any():
         raise ValueError("no observed voxel")
@@ -228,13 +246,17 @@ def shell_power(s_hat, prob: Problem) -> np.ndarray:
 
 
 def power_step(sigma, p_grid, prob: Problem, sweep: int) -> np.ndarray:
-    """Draw P_b (grid units) from InvGamma(n_b/2, sigma_b/(2M)); empty bins keep P."""
+    """Draw P_b (grid units) from InvGamma(n_b/2 + a0, sigma_b/(2M) + b0), the
+    conditional under the InvGamma(a0, b0) prior (Jeffreys' at a0 = b0 = 0);
+    empty bins keep P."""
     counts = shells.mode_counts(prob.n, prob.n_bins)
     out = np.array(p_grid, dtype=np.float64, copy=True)
+    b0 = prob.prior_scale_grid
     for b in range(prob.n_bins):
         if counts[b] > 0:
-            g = philox.gamma_mt(0.5 * counts[b], prob.seed, prob.chain, sweep, b)
-            out[b] = sigma[b] / (2.0 * prob.m * g)
+            g = philox.gamma_mt(0.5 * counts[b] + prob.prior_shape, prob.seed, prob.chain,
+                                sweep, b)
+            out[b] = (sigma[b] + 2.0 * prob.m * b0) / (2.0 * prob.m * g)
     return out
 
 

@@ -19,16 +19,18 @@ from oracle import mixing, sampler, shells
 from paper_1402_1763_amd import workloads
 
 
-def _log_post(p, sum_t2, n_modes, m, tau):
+def _log_post(p, sum_t2, n_modes, m, tau, a0=0.0, b0=0.0):
+    """ln of prior(P) prod_k N(t^_k; 0, M (P + tau)) up to a constant, with the
+    InvGamma(a0, b0) prior P^-(a0+1) exp(-b0/P) (grid units; Jeffreys' at 0, 0)."""
     v = m * (p + tau)
-    return -np.log(p) - 0.5 * n_modes * np.log(v) - 0.5 * sum_t2 / v
+    return -(a0 + 1.0) * np.log(p) - b0 / p - 0.5 * n_modes * np.log(v) - 0.5 * sum_t2 / v
 
 
-def _quadrature_moments(sum_t2, n_modes, m, tau):
+def _quadrature_moments(sum_t2, n_modes, m, tau, a0=0.0, b0=0.0):
     """E[ln P] and Var[ln P] under p(P | t^), integrating over y = ln P."""
     y = np.linspace(-12, 12, 200001)
     p = np.exp(y)
-    lp = _log_post(p, sum_t2, n_modes, m, tau) + y          # density in y
+    lp = _log_post(p, sum_t2, n_modes, m, tau, a0, b0) + y          # density in y
     w = np.exp(lp - lp.max())
     z = scipy.integrate.trapezoid(w, y)
     mean = scipy.integrate.trapezoid(w * y, y) / z
@@ -36,10 +38,11 @@ def _quadrature_moments(sum_t2, n_modes, m, tau):
     return mean, var
 
 
-def _fixed_t_problem(n=8, n_bins=3, seed=3):
+def _fixed_t_problem(n=8, n_bins=3, seed=3, prior=(0.0, 0.0)):
     w = workloads.small_workload(n, n_bins, mask="none", seed=seed, sigma2=1.0, box=15.625 * n)
     pb = workloads.make_problem(w)
-    prob = sampler.make_problem(pb["data"], np.full((n,) * 3, 1.0), n_bins, w.box, seed=9)
+    prob = sampler.make_problem(pb["data"], np.full((n,) * 3, 1.0), n_bins, w.box, seed=9,
+                                prior=prior)
     rng = np.random.default_rng(seed)
     t = rng.standard_normal((n,) * 3) * 1.7          # a messenger field of variance ~ P + tau
     return prob, np.fft.rfftn(t)
@@ -88,7 +91,8 @@ def _check(logs, prob, t_hat):
     for b in range(prob.n_bins):
         sel = b_of == b
         sum_t2 = float(np.sum((np.abs(t_hat) ** 2 * w)[sel]))
-        mean, var = _quadrature_moments(sum_t2, counts[b], prob.m, prob.tau)
+        mean, var = _quadrature_moments(sum_t2, counts[b], prob.m, prob.tau, prob.prior_shape,
+                                        prob.prior_scale / prob.cell_volume)
         x = logs[burn:, b]
         batches = x[: len(x) // 50 * 50].reshape(50, -1).mean(axis=1)
         se = batches.std(ddof=1) / np.sqrt(50)
@@ -100,12 +104,32 @@ def _check(logs, prob, t_hat):
 ITERS = 20000    # the correct rule stays within |z| < 1 here; the controls reach 6 to 25
 
 
-def test_mixing_update_leaves_the_exact_conditional_invariant():
-    prob, t_hat = _fixed_t_problem()
+# a proper InvGamma prior strong enough to move the conditional: b0 of 1.2
+# in grid units against sum |t^|^2 / (M n_b) of about 3
+PROPER_PRIOR = (2.0, 1.2 * 15.625 ** 3)
+
+
+@pytest.mark.parametrize("prior", [(0.0, 0.0), PROPER_PRIOR])
+def test_mixing_update_leaves_the_exact_conditional_invariant(prior):
+    prob, t_hat = _fixed_t_problem(prior=prior)
     logs = _run(prob, t_hat, [1.0] * prob.n_bins, ITERS)
     z = _check(logs, prob, t_hat)
     print("z-scores", z)
     assert np.all(np.abs(z) < 4.0)
+
+
+def test_jeffreys_rule_fails_under_a_proper_prior():
+    """The prior enters the acceptance: Jeffreys' rule U/U' run on a problem
+    with the proper prior misses that prior's conditional."""
+    prob, t_hat = _fixed_t_problem(prior=PROPER_PRIOR)
+    jeffreys = _fixed_t_problem()[0]
+
+    def step(s_hat, t_hat, p, prob_, sweep):
+        return mixing.mix_power_step(s_hat, t_hat, p, jeffreys, sweep)[0]
+    logs = _run(prob, t_hat, [1.0] * prob.n_bins, ITERS, accept_rule=step)
+    with pytest.raises(AssertionError):
+        z = _check(logs, prob, t_hat)
+        assert np.all(np.abs(z) < 4.0)
 
 
 @pytest.mark.parametrize("kind", ["squared", "always"])

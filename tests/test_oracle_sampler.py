@@ -101,9 +101,20 @@ def test_uniform_noise_one_sweep_is_textbook_wiener():
     assert abs(diag["s_hat"][k] - expect) < 1e-12 * abs(expect)
 
 
-def test_power_draw_is_inverse_gamma():
+# (a0, b0): Jeffreys' prior, and proper InvGamma priors whose scale is small,
+# comparable with, and far above sigma_b / 2M of the bins (b0 in physical units)
+PRIORS = [(0.0, 0.0), (1.5, 2.0e3), (0.0, 5.0e4), (3.0, 2.0e6)]
+
+
+@pytest.mark.parametrize("prior", PRIORS)
+def test_power_draw_is_inverse_gamma(prior):
+    """P_b | s ~ InvGamma(n_b/2 + a0, sigma_b/(2M) + b0) in grid units: KS
+    against scipy's inverse gamma, whose shape and scale are written out here
+    from the conjugate update, not taken from the oracle."""
     n, nbins = 16, 5
-    w, pb, prob = _problem(n, nbins)
+    w, pb, prob0 = _problem(n, nbins)
+    prob = sampler.make_problem(pb["data"], pb["noise_var"], nbins, w.box, seed=prob0.seed,
+                                prior=prior)
     rng = np.random.default_rng(3)
     s_hat = np.fft.rfftn(rng.standard_normal((n,) * 3) * 2.0)
     sigma = sampler.shell_power(s_hat, prob)
@@ -112,9 +123,29 @@ def test_power_draw_is_inverse_gamma():
     for sweep in range(400):
         draws.append(sampler.power_step(sigma, np.ones(nbins), prob, sweep))
     draws = np.array(draws)
+    a0, b0 = prior
+    vcell = (w.box / n) ** 3
     for b in range(nbins):
-        dist = scipy.stats.invgamma(counts[b] / 2.0, scale=sigma[b] / (2.0 * prob.m))
+        dist = scipy.stats.invgamma(counts[b] / 2.0 + a0,
+                                    scale=sigma[b] / (2.0 * prob.m) + b0 / vcell)
         assert scipy.stats.kstest(draws[:, b], dist.cdf).pvalue > 1e-3
+
+
+def test_power_draw_prior_changes_the_draw():
+    """The prior must act: with b0 far above sigma_b / 2M the draws follow the
+    prior scale, and Jeffreys' draws fail that distribution's KS test."""
+    n, nbins = 16, 5
+    w, pb, prob0 = _problem(n, nbins)
+    a0, b0 = PRIORS[-1]
+    rng = np.random.default_rng(3)
+    s_hat = np.fft.rfftn(rng.standard_normal((n,) * 3) * 2.0)
+    sigma = sampler.shell_power(s_hat, prob0)
+    counts = shells.mode_counts(n, nbins)
+    draws = np.array([sampler.power_step(sigma, np.ones(nbins), prob0, sweep)
+                      for sweep in range(400)])
+    vcell = (w.box / n) ** 3
+    dist = scipy.stats.invgamma(counts[0] / 2.0 + a0, scale=sigma[0] / (2.0 * prob0.m) + b0 / vcell)
+    assert scipy.stats.kstest(draws[:, 0], dist.cdf).pvalue < 1e-6
 
 
 def test_shell_power_is_full_grid_sum_and_parseval():
