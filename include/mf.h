@@ -76,6 +76,17 @@ typedef struct {
   int32_t n_chains;   /* independent chains sharing N, bins, box and seed (>= 1) */
   int32_t has_response; /* 1: mf_init_problem takes a per-voxel response R per
                            chain; 0: R = 1 on every observed voxel */
+  /* Prior on every P_b: the conjugate InvGamma(a0, b0), density
+   * ~ P^-(a0+1) exp(-b0 / P), with a0 = pk_prior_shape >= 0 and
+   * b0 = pk_prior_scale >= 0 in physical units (volume).  (0, 0) is Jeffreys'
+   * prior 1/P of Sec. 3.2, the paper's choice, under which the joint
+   * posterior is improper as P_b -> 0 wherever the noise is finite; b0 > 0
+   * makes it proper.  The P step then draws InvGamma(n_b/2 + a0,
+   * sigma_b/(2M) + b0 / V_cell) in grid units, and the mixing sweep's
+   * Metropolis-Hastings move accepts with min(1, (U/U')^(2 a0 + 1)
+   * exp(M b0 / V_cell (1/U^2 - 1/U'^2))). */
+  double pk_prior_shape;
+  double pk_prior_scale;
 } mf_chain_desc;
 
 typedef struct mf_problem mf_problem;
@@ -135,6 +146,20 @@ mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
  * sweeps (NaN for a kernel never timed: n_sweeps < MF_NUM_KERNELS). */
 mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream,
                                double* kernel_ms, int32_t n_kernels);
+
+/* As mf_gibbs_sweep_timed, with every timed kernel preceded by a copy of the
+ * first half of the caller's device buffer `evict` onto its second half.  A
+ * buffer several times the device's last-level (fabric) cache, 256 MB on
+ * MI355X, leaves that cache holding none of the kernel's data, so the times
+ * are those of passes that find their inputs in DRAM only; the difference to
+ * mf_gibbs_sweep_timed is what the cache gives each pass.  The copies are not
+ * inside the timed intervals.  The chain advances as with mf_gibbs_sweep.
+ * Errors: as mf_gibbs_sweep_timed, and MF_E_INVALID_ARG for an eviction
+ * buffer that is NULL, not 16-byte aligned, not a multiple of 32 bytes or
+ * smaller than 64 MiB. */
+mf_status mf_gibbs_sweep_timed_cold(mf_problem* p, int32_t n_sweeps, void* stream,
+                                    double* kernel_ms, int32_t n_kernels, void* evict,
+                                    size_t evict_bytes);
 
 /* Copy chain `chain`'s state to the host: s_out (M doubles, may be NULL),
  * pk_out (n_bins doubles, physical units, may be NULL), sweep_out (number of
@@ -340,6 +365,27 @@ mf_status mf_wiener_logdet_workspace_bytes(const mf_problem* p, int32_t chain, s
 mf_status mf_wiener_logdet_trace(mf_problem* p, int32_t chain, const double* pk, int32_t n_iter,
                                  int32_t n_probes, uint32_t probe0, void* workspace,
                                  size_t ws_bytes, double* trace_out, void* stream);
+
+/* For callers that cannot allocate device memory (code being captured into
+ * a HIP graph, serving loops, harnesses that forbid allocation):
+ * mf_wiener_logdet_trace without the workspace argument.  The estimator's
+ * scratch (the size mf_wiener_logdet_workspace_bytes reports) lives in a
+ * static device array of MF_LOGDET_SCRATCH_BYTES (64 MiB) inside the
+ * library, one per device, held from the first call on that device until the
+ * process ends; the call allocates nothing.  That covers one 128^3 FP32
+ * chain, or several chains at 64^3.  Arguments, results and the other errors
+ * are those of mf_wiener_logdet_trace, with the problem on the calling
+ * thread's current device.  Every call on a device uses the same array and
+ * rewrites all of it that it reads, so calls do not see each other's
+ * results; calls that overlap in time on one device (other streams or host
+ * threads) race on it and must be serialised by the caller.
+ * Errors: MF_E_WORKSPACE when the estimate needs more scratch than
+ * MF_LOGDET_SCRATCH_BYTES, MF_E_DEVICE if the array's address cannot be
+ * found, and those of mf_wiener_logdet_trace. */
+#define MF_LOGDET_SCRATCH_BYTES (64ull << 20)
+mf_status mf_wiener_logdet_trace_noalloc(mf_problem* p, int32_t chain, const double* pk,
+                                         int32_t n_iter, int32_t n_probes, uint32_t probe0,
+                                         double* trace_out, void* stream);
 
 /* Streaming reference for the roofline (not part of the sampler): what
  * plain HBM streaming reaches on the device.  mode 0 copies `bytes` from src

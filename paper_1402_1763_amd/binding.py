@@ -47,6 +47,8 @@ class mf_chain_desc(ctypes.Structure):
         ("sample_pk", ctypes.c_int32),
         ("n_chains", ctypes.c_int32),
         ("has_response", ctypes.c_int32),
+        ("pk_prior_shape", ctypes.c_double),
+        ("pk_prior_scale", ctypes.c_double),
     ]
 
 
@@ -62,6 +64,9 @@ SIGNATURES = {
     "mf_mixing_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mf_gibbs_sweep_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             _c_double_p, ctypes.c_int32]),
+    "mf_gibbs_sweep_timed_cold": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.c_void_p, _c_double_p, ctypes.c_int32,
+                                                 ctypes.c_void_p, ctypes.c_size_t]),
     "mf_get_chain_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
                                           _c_double_p, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.c_void_p]),
@@ -101,6 +106,10 @@ SIGNATURES = {
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                               ctypes.c_void_p]),
+    "mf_wiener_logdet_trace_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                                      ctypes.c_void_p, ctypes.c_int32,
+                                                      ctypes.c_int32, ctypes.c_uint32,
+                                                      ctypes.c_void_p, ctypes.c_void_p]),
     "mf_stream_reference": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "mf_diagnostics_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
@@ -161,11 +170,13 @@ def _ptr_array(arrays):
 
 def make_desc(n: int, n_bins: int, box: float, seed: int, precision: str = "fp32",
               tau: float = 0.0, chain_id: int = 0, sample_pk: bool = True,
-              n_chains: int = 1, has_response: bool = False) -> mf_chain_desc:
+              n_chains: int = 1, has_response: bool = False,
+              pk_prior=(0.0, 0.0)) -> mf_chain_desc:
     prec = {"fp64": MF_PREC_FP64, "fp32": MF_PREC_FP32}[precision]
     return mf_chain_desc(n=n, n_bins=n_bins, box=box, tau=tau, seed=seed, chain_id=chain_id,
                          precision=prec, sample_pk=1 if sample_pk else 0, n_chains=n_chains,
-                         has_response=1 if has_response else 0)
+                         has_response=1 if has_response else 0,
+                         pk_prior_shape=float(pk_prior[0]), pk_prior_scale=float(pk_prior[1]))
 
 
 def mf_supported_n(n: int) -> bool:
@@ -345,11 +356,13 @@ class Sampler:
     chain); noise_var = +inf marks unobserved voxels.  response: None (R = 1)
     or the per-voxel response R of the data model d = R s + eps, in the same
     form (R = 0 also marks unobserved voxels).  pk_init: initial P per bin in
-    physical units."""
+    physical units.  pk_prior: (a0, b0) of the InvGamma prior on P, b0 in
+    physical units; (0, 0) is Jeffreys' prior."""
 
     def __init__(self, data, noise_var, pk_init, n_bins: int, box: float, seed: int,
                  precision: str = "fp32", tau: float = 0.0, chain_id: int = 0,
-                 sample_pk: bool = True, s_init=None, device: str = "cuda", response=None):
+                 sample_pk: bool = True, s_init=None, device: str = "cuda", response=None,
+                 pk_prior=(0.0, 0.0)):
         import torch
         multi = isinstance(data, (list, tuple))
         data_l = list(data) if multi else [data]
@@ -361,7 +374,8 @@ class Sampler:
         self.n_bins = n_bins
         self.n_chains = len(data_l)
         self.desc = make_desc(self.n, n_bins, box, seed, precision, tau, chain_id, sample_pk,
-                              self.n_chains, has_response=response is not None)
+                              self.n_chains, has_response=response is not None,
+                              pk_prior=pk_prior)
         self.workspace_bytes = mf_workspace_bytes(self.desc)
         self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
@@ -380,6 +394,17 @@ class Sampler:
 
     def sweep_timed(self, n_sweeps: int) -> np.ndarray:
         return mf_gibbs_sweep_timed(self.handle, n_sweeps, self.stream.cuda_stream)
+
+    def sweep_timed_cold(self, n_sweeps: int, evict) -> np.ndarray:
+        """Per-kernel mean ms, every timed kernel started after `evict` (a cuda
+        tensor far larger than the last-level cache) was streamed through."""
+        out = np.zeros(MF_NUM_KERNELS, dtype=np.float64)
+        nbytes = evict.numel() * evict.element_size() // 32 * 32
+        _check(load().mf_gibbs_sweep_timed_cold(ctypes.c_void_p(self.handle), n_sweeps,
+                                                ctypes.c_void_p(self.stream.cuda_stream),
+                                                _dptr(out), MF_NUM_KERNELS,
+                                                ctypes.c_void_p(evict.data_ptr()), nbytes))
+        return out
 
     def state(self, chain: int = 0, want_s: bool = True):
         return mf_get_chain_state(self.handle, chain, self.n, self.n_bins,

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -150,6 +151,9 @@ mf_status check_desc(const mf_chain_desc* d) {
   if (std::isnan(d->tau)) return fail(MF_E_INVALID_ARG, "tau is NaN");
   if (d->has_response != 0 && d->has_response != 1)
     return fail(MF_E_INVALID_ARG, "has_response must be 0 or 1");
+  if (!std::isfinite(d->pk_prior_shape) || !std::isfinite(d->pk_prior_scale) ||
+      d->pk_prior_shape < 0.0 || d->pk_prior_scale < 0.0)
+    return fail(MF_E_INVALID_ARG, "the InvGamma prior (a0, b0) on P needs finite a0, b0 >= 0");
   return MF_OK;
 }
 
@@ -275,6 +279,8 @@ mf::SweepArgs<R> args_of(const mf_problem* p, int path = -1) {
   a.diag_thin = p->diag.thin;
   a.trace_cap = p->diag.cap;
   a.vcell = std::pow(p->desc.box / p->desc.n, 3);
+  a.prior_a = p->desc.pk_prior_shape;
+  a.prior_b = p->desc.pk_prior_scale / a.vcell;
   return a;
 }
 
@@ -749,22 +755,34 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream) {
   return MF_OK;
 }
 
-mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, double* kernel_ms,
-                               int32_t n_kernels) {
+}  // extern "C"
+
+namespace {
+
+// Gibbs sweeps with kernel i mod MF_NUM_KERNELS of sweep i timed by one pair
+// of events that skip the system-scope fence (a cache write-back and
+// invalidate at every event would slow the kernels being timed).  With an
+// eviction buffer, its first half is copied onto its second half just before
+// each timed kernel, so that the kernel starts with the fabric's last-level
+// cache holding none of its data.
+mf_status timed_sweeps(mf_problem* p, int32_t n_sweeps, hipStream_t hs, double* kernel_ms,
+                       int32_t n_kernels, void* evict, size_t evict_bytes) {
   if (!p || !kernel_ms || n_kernels < 0) return fail(MF_E_INVALID_ARG, "bad argument");
   if (n_sweeps <= 0) return fail(MF_E_INVALID_ARG, "need at least one sweep");
   const mf_status room = check_sweep_room(p, n_sweeps);
   if (room != MF_OK) return room;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  // Sweep i brackets only its kernel i mod MF_NUM_KERNELS, with one pair of
-  // events that skip the system-scope fence (a cache write-back and
-  // invalidate at every event would slow the kernels being timed).
+  const size_t half16 = evict_bytes / 32;   // 16-byte vectors per half
   std::vector<hipEvent_t> ev(static_cast<size_t>(n_sweeps) * 2);
   for (auto& e : ev) MF_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   mf_status st = MF_OK;
   for (int i = 0; i < n_sweeps && st == MF_OK; ++i) {
     const int timed = i % MF_NUM_KERNELS;
     for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k) {
+      if (k == timed && evict) {
+        const auto* src = static_cast<const mf::v4u*>(evict);
+        hipLaunchKernelGGL(mf::stream_copy_kernel<false>, dim3(16384), dim3(mf::kStreamThreads),
+                           0, hs, src, static_cast<mf::v4u*>(evict) + half16, half16);
+      }
       if (k == timed) MF_HIP(hipEventRecord(ev[2 * i], hs));
       st = launch_checked(p, kSweepOrder[k], 0, hs);
       if (st == MF_OK && k == timed) MF_HIP(hipEventRecord(ev[2 * i + 1], hs));
@@ -786,6 +804,27 @@ mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, do
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, double* kernel_ms,
+                               int32_t n_kernels) {
+  return timed_sweeps(p, n_sweeps, static_cast<hipStream_t>(stream), kernel_ms, n_kernels,
+                      nullptr, 0);
+}
+
+mf_status mf_gibbs_sweep_timed_cold(mf_problem* p, int32_t n_sweeps, void* stream,
+                                    double* kernel_ms, int32_t n_kernels, void* evict,
+                                    size_t evict_bytes) {
+  if (!evict || reinterpret_cast<uintptr_t>(evict) % 16 != 0 || evict_bytes < (64u << 20) ||
+      evict_bytes % 32 != 0)
+    return fail(MF_E_INVALID_ARG, "eviction buffer: 16-byte aligned, a multiple of 32 bytes, "
+                "at least 64 MiB");
+  return timed_sweeps(p, n_sweeps, static_cast<hipStream_t>(stream), kernel_ms, n_kernels,
+                      evict, evict_bytes);
 }
 
 mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double* pk_out,
@@ -1600,6 +1639,72 @@ mf_status mf_wiener_logdet_trace(mf_problem* p, int32_t chain, const double* pk,
   char* g = static_cast<char*>(workspace);
   return p->fp64() ? logdet_run<double>(p, c0, pk, n_iter, n_probes, probe0, g, L, trace_out, hs)
                    : logdet_run<float>(p, c0, pk, n_iter, n_probes, probe0, g, L, trace_out, hs);
+}
+
+}  // extern "C"
+
+// ------------------------------------------- log-determinant trace without allocation
+namespace {
+
+// Scratch of mf_wiener_logdet_trace_noalloc: the estimator's workspace in a
+// device array of the library's own, so that the call allocates nothing.
+// Every device the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the
+// device's memory: kernels and copies take the address from
+// hipGetSymbolAddress (scratch_address), kept per device.
+static __device__ __align__(256) unsigned char scratch[MF_LOGDET_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the calling thread's current device, looked
+// up on that device's first call and kept.
+mf_status scratch_address(void** out) {
+  int dev = -1;
+  MF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(MF_E_DEVICE, "device %d outside the %d devices the scratch table covers", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    MF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign != 0)
+      return fail(MF_E_DEVICE, "scratch array of device %d has no usable address", dev);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_wiener_logdet_trace_noalloc(mf_problem* p, int32_t chain, const double* pk,
+                                         int32_t n_iter, int32_t n_probes, uint32_t probe0,
+                                         double* trace_out, void* stream) {
+  if (!p) return fail(MF_E_INVALID_ARG, "problem is NULL");
+  if (p->desc.n < 32 || p->desc.n > 256)
+    return fail(MF_E_UNSUPPORTED_SIZE, "the Wiener iteration supports grid sides 32 to 256 (got %d)",
+                p->desc.n);
+  int c0 = 0, nc = 0;
+  mf_status r = wiener_chains(p, chain, &c0, &nc);
+  if (r != MF_OK) return r;
+  if (n_iter < 1 || n_probes < 1) return fail(MF_E_INVALID_ARG, "need n_iter >= 1 and n_probes >= 1");
+  if (!pk || !trace_out) return fail(MF_E_INVALID_ARG, "pk and trace_out must be device pointers");
+  const LLayout L = logdet_layout(p, nc);
+  if (L.total > static_cast<size_t>(MF_LOGDET_SCRATCH_BYTES))
+    return fail(MF_E_WORKSPACE, "this estimate needs %zu bytes of scratch; the library's static "
+                "scratch holds %zu (use mf_wiener_logdet_trace with a workspace)", L.total,
+                static_cast<size_t>(MF_LOGDET_SCRATCH_BYTES));
+  void* g = nullptr;
+  if ((r = scratch_address(&g)) != MF_OK) return r;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* gc = static_cast<char*>(g);
+  return p->fp64() ? logdet_run<double>(p, c0, pk, n_iter, n_probes, probe0, gc, L, trace_out, hs)
+                   : logdet_run<float>(p, c0, pk, n_iter, n_probes, probe0, gc, L, trace_out, hs);
 }
 
 }  // extern "C"

@@ -77,6 +77,9 @@ struct SweepArgs {
   int32_t diag_thin;
   int32_t trace_cap;
   double vcell;
+  // InvGamma(prior_a, prior_b) prior on P_b, prior_b in grid units; (0, 0) is
+  // Jeffreys' prior
+  double prior_a, prior_b;
 };
 
 // Index j of sample `sweep` among the recorded ones, or -1.
@@ -421,12 +424,6 @@ __device__ __forceinline__ void write_table(R* tab, int b, double p, double tau,
   tab[2 * b + 1] = static_cast<R>(sqrt(tau * f / (2.0 * m)));
 }
 
-// P(k) step of bin b of chain c by one workgroup of NTH threads: sums the x-pass partials in a fixed order (strided per thread, then a
-// tree in `red`, NTH doubles), forms sigma_b = M^2 sum w |s^/M|^2 and draws
-// P_b = sigma_b / (2 M g), g ~ Gamma(n_b / 2, 1) -- the inverse-gamma
-// conditional of P_b under Jeffreys' prior -- then refreshes (A_b, B_b).
-// With pk_mode == kPkGrad the workgroup instead adds sum_wg partials / M to
-// gacc[b] (the Wiener adjoint's d chi2 / d f_b); kPkNone does nothing.
 // Sum of n per-workgroup partials in a fixed order by one workgroup of NTH
 // threads: strided per thread, then a tree in `red` (NTH doubles) folded onto
 // the largest power of two <= NTH.  The result is red[0] (all threads).
@@ -449,6 +446,14 @@ __device__ __forceinline__ double sum_partials(const double* part, int n, double
   return red[0];
 }
 
+// P(k) step of bin b of chain c by one workgroup of NTH threads: sums the
+// x-pass partials in a fixed order (sum_partials), forms
+// sigma_b = M^2 sum w |s^/M|^2 and draws P_b = (sigma_b + 2 M b0) / (2 M g),
+// g ~ Gamma(n_b / 2 + a0, 1) -- the inverse-gamma conditional of P_b under
+// the InvGamma(a0, b0) prior, Jeffreys' prior at a0 = b0 = 0 -- then refreshes
+// (A_b, B_b).  With pk_mode == kPkGrad the workgroup instead adds
+// sum_wg partials / M to gacc[b] (the Wiener adjoint's d chi2 / d f_b);
+// kPkNone does nothing.
 template <typename R, int NTH>
 __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int c, double* red) {
   if (a.pk_mode == kPkNone) return;
@@ -468,9 +473,9 @@ __device__ __forceinline__ void pk_draw_block(const SweepArgs<R>& a, int b, int 
         a.trace[(static_cast<size_t>(c) * a.trace_cap + j) * a.nb + b] = p * a.vcell;
     }
     if (a.sample_pk && a.counts[b] > 0.0) {
-      const double g = gamma_mt(0.5 * a.counts[b], static_cast<uint32_t>(b), a.ctr[1],
+      const double g = gamma_mt(0.5 * a.counts[b] + a.prior_a, static_cast<uint32_t>(b), a.ctr[1],
                                 a.chain0 + c, a.key0, a.key1);
-      p = sigma / (2.0 * m * g);
+      p = (sigma + 2.0 * m * a.prior_b) / (2.0 * m * g);
       if (!(g > 0.0) || !isfinite(p) || !isfinite(sigma)) {
         atomicOr(a.status + c, 1u);
         p = pk[b];
@@ -533,9 +538,11 @@ __device__ inline bool truncated_normal(double mean, double sd, uint32_t b, uint
 // current P by the x-pass, H1 = sum w |y|^2 and H2 = sum w Re(conj(y) t^)
 // (partials and partials2) give, for x^ = s^ / sqrt(S^),
 //   X = sum |x^|^2 = M H1 / P,   R = sum Re(conj(x^) t^) = M H2 / sqrt(S^).
-// U = sqrt(S^) has conditional density ~ U^-1 N(U; R/X, T^/X), T^ = M tau;
-// the proposal U' ~ N(R/X, T^/X) truncated to U' > 0 is accepted with
-// probability min(1, U/U').  Writes the new P, its table and the factor
+// U = sqrt(S^) has conditional density ~ U^-1 N(U; R/X, T^/X), T^ = M tau,
+// under Jeffreys' prior, and ~ U^-(2 a0 + 1) exp(-M b0 / U^2) N(U; R/X, T^/X)
+// under the InvGamma(a0, b0) prior; the proposal U' ~ N(R/X, T^/X) truncated
+// to U' > 0 is accepted with probability min(1, U/U'), respectively
+// min(1, (U/U')^(2 a0 + 1) exp(M b0 (1/U^2 - 1/U'^2))) (in logarithms).  Writes the new P, its table and the factor
 // ratio = U'/U (1 if rejected) by which the x-pass output is rescaled.
 template <typename R>
 __global__ void __launch_bounds__(256)
@@ -561,9 +568,18 @@ mix_pk_kernel(SweepArgs<R> a) {
     const double u = sqrt(m * p);
     const double xx = m * h1 / p, xt = m * h2 / u;
     double u_new = 0.0, u_mh = 1.0;
-    if (truncated_normal(xt / xx, sqrt(m * tau / xx), static_cast<uint32_t>(b), sweep,
-                         a.chain0 + c, a.key0, a.key1, u_new, u_mh) &&
-        u_mh <= u / u_new) {
+    bool ok = truncated_normal(xt / xx, sqrt(m * tau / xx), static_cast<uint32_t>(b), sweep,
+                               a.chain0 + c, a.key0, a.key1, u_new, u_mh);
+    if (ok) {
+      if (a.prior_a == 0.0 && a.prior_b == 0.0) {
+        ok = u_mh <= u / u_new;
+      } else {
+        const double lr = (2.0 * a.prior_a + 1.0) * log(u / u_new) +
+                          m * a.prior_b * (1.0 / (u * u) - 1.0 / (u_new * u_new));
+        ok = log(u_mh) <= lr;
+      }
+    }
+    if (ok) {
       p_new = u_new * u_new / m;
       ratio = u_new / u;
     }

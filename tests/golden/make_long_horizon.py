@@ -33,7 +33,7 @@ SAMPLE_SEED = 4242
 
 def path_of(name: str) -> str:
     return os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                        f"long_horizon_{name.split('-')[1].replace('^', '')}.json")
+                        f"long_horizon_{name.split('-')[1].split('^')[0]}.json")
 
 
 def run(name: str) -> None:

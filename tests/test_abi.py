@@ -59,6 +59,18 @@ def test_workspace_bytes_and_descriptor_errors(lib):
         binding.mf_workspace_bytes(d)
 
 
+def test_pk_prior_must_be_finite_and_non_negative(lib):
+    """The InvGamma(a0, b0) prior on P: (0, 0) is Jeffreys' prior; negative
+    or non-finite values are refused when the descriptor is checked."""
+    ok = binding.make_desc(32, 16, 500.0, 1, pk_prior=(1.5, 4.0e5))
+    assert binding.mf_workspace_bytes(ok) == binding.mf_workspace_bytes(
+        binding.make_desc(32, 16, 500.0, 1))
+    for bad in ((-1.0, 0.0), (0.0, -2.0), (float("nan"), 0.0), (0.0, float("inf"))):
+        with pytest.raises(binding.MFError) as e:
+            binding.mf_workspace_bytes(binding.make_desc(32, 16, 500.0, 1, pk_prior=bad))
+        assert e.value.status == binding.MF_E_INVALID_ARG
+
+
 def _init(desc, data, noise, pk, ws_ptr=256, ws_bytes=1 << 40):
     return binding.mf_init_problem(desc, [data], [noise], [pk], None, ws_ptr, ws_bytes, stream=0)
 
