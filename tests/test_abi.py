@@ -168,3 +168,19 @@ def test_null_handles_are_rejected(lib):
     assert lib.mf_wiener_logdet_workspace_bytes(None, 0, None) == binding.MF_E_INVALID_ARG
     lib.mf_destroy_problem(None)
     lib.mf_graph_destroy(None)
+
+
+def test_init_without_a_device_fails_after_the_host_set_up(lib):
+    """With valid inputs the host set-up (validation, tau, bin thresholds, mode
+    counts, twiddles) runs, then the first device call fails: MF_E_DEVICE and
+    no handle.  Only where no GPU is visible."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible; the fake workspace pointer must not reach it")
+    for n, nb, prec in ((8, 4, "fp64"), (48, 16, "fp32")):
+        w = workloads.small_workload(n, nb)
+        pb = workloads.make_problem(w)
+        desc = binding.make_desc(n, nb, w.box, 1, prec, pk_prior=(0.5, 10.0))
+        with pytest.raises(binding.MFError) as e:
+            _init(desc, pb["data"], pb["noise_var"], pb["pk_init"])
+        assert e.value.status == binding.MF_E_DEVICE
