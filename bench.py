@@ -100,6 +100,10 @@ def cpu_baseline(w, pb, max_seconds: float = 30.0):
                       f"replaced by its mean"}
 
 
+def _r5(v):
+    return None if v != v else round(float(v), 5)
+
+
 def bench_batched(args):
     """Independent chains of sides 64 (32 chains), 48, 80 and 96 (8 chains each),
     FP32, 16 bins: one HIP graph replay sweeps all 56 chains once."""
@@ -116,21 +120,33 @@ def bench_batched(args):
                                         seed=ws[0].rng_seed, chain_id=1000 * n, precision="fp32"))
         chain_voxels += chains * n ** 3
         sweep_bytes += sum(samplers[-1].sweep_bytes().values())
-    tuned = {}
-    for (n, _), smp in zip(workloads.BATCHED_SIZES, samplers):
-        tuned[f"{n}^3"] = smp.autotune(trials=10)["path"]   # before the graph is captured
-    graph = binding.SweepGraph(samplers)
     stream = torch.cuda.current_stream()
-    graph.launch(args.warmup)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def graph_ms():
+        g = binding.SweepGraph(samplers)
+        g.launch(args.warmup)
+        torch.cuda.synchronize()
+        start.record(stream)
+        g.launch(args.steps)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        g.close()
+        return start.elapsed_time(stop) / args.steps
+
+    # the library's default tiles, for comparison on the same device
     for smp in samplers:
         smp.sweep(args.warmup)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    graph.launch(args.steps)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    ms_defaults = graph_ms()
+    tuned = {}
+    for (n, _), smp in zip(workloads.BATCHED_SIZES, samplers):
+        res = smp.autotune(trials=10)                         # before the graph is captured
+        tuned[f"{n}^3"] = {k: res[k] for k in ("path", "x_tile", "y_group", "x_cols", "x_k1",
+                                                "y_units")}
+        tuned[f"{n}^3"]["ms"] = {"path": {k: _r5(v) for k, v in res["ms"].items()},
+                                 "x_tile": [_r5(v) for v in res["ms_x_tile"]],
+                                 "y_group": [_r5(v) for v in res["ms_y_group"]]}
+    ms = graph_ms()
     start.record(stream)
     for _ in range(args.steps):
         for smp in samplers:
@@ -141,7 +157,6 @@ def bench_batched(args):
     for smp in samplers:
         _, pk, _ = smp.state(want_s=False)
         assert np.all(np.isfinite(pk))
-    graph.close()
     # the plain way: every chain its own single-chain problem, swept in turn
     singles = []
     for n, chains in workloads.BATCHED_SIZES:
@@ -173,7 +188,9 @@ def bench_batched(args):
         "data": "synthetic",
         "config": {"workload": "gibbs-batched-mixed",
                    "chains": {f"{n}^3": c for n, c in workloads.BATCHED_SIZES},
-                   "x_path": tuned,
+                   "tuning": tuned,
+                   "default_tiles_ms_per_step": round(ms_defaults, 5),
+                   "tuned_speedup_vs_default_tiles": round(ms_defaults / ms, 4),
                    "chain_sweeps_per_s": round(chains * 1000.0 / ms, 1),
                    "voxel_sweeps_per_s": round(chain_voxels * 1000.0 / ms, 1),
                    "sweep_bytes_algorithmic": sweep_bytes,
@@ -265,11 +282,19 @@ def plain_sweep_ms(w, pb, steps: int, precision: str = "fp32") -> float:
     return start.elapsed_time(stop) / steps
 
 
+# Prior on P(k) of the chain-efficiency runs besides Jeffreys': InvGamma with
+# a0 = 0 and b0 = 50 h^-3 Mpc^3, a log-uniform prior cut off below about
+# b0, well under the truth of every bin of the 128^3 survey (about 90 at the
+# highest k); it makes the joint posterior proper as P -> 0.
+EFFICIENCY_PRIOR = (0.0, 50.0)
+
+
 def bench_chain_efficiency(args):
     """Statistical efficiency on the 128^3 survey problem (Sec. 5.1): after a
     burn-in, record every 10th of `steps` sweeps of P(k) and compute the
     autocorrelation and the ten-percent correlation length n_c of every bin,
-    for Gibbs sweeps and for mixing sweeps (Alg. 3)."""
+    for Gibbs sweeps, mixing sweeps (Alg. 3) and the two alternating, under
+    Jeffreys' prior and under the proper InvGamma prior EFFICIENCY_PRIOR."""
     import torch
 
     from paper_1402_1763_amd import binding, workloads
@@ -279,48 +304,54 @@ def bench_chain_efficiency(args):
     thin, burn = 10, args.warmup
     cap = args.steps // thin
     truth = workloads.power_spectrum(workloads.bin_centres(w), w)
-    out_runs = {}
-    for kind in ("gibbs", "mixing", "alternating"):
-        smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
-                              seed=w.rng_seed, precision="fp32")
+    runs = {}
+    for prior_name, prior in (("jeffreys", (0.0, 0.0)), ("invgamma", EFFICIENCY_PRIOR)):
+        out_runs = {}
+        for kind in ("gibbs", "mixing", "alternating"):
+            smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                                  seed=w.rng_seed, precision="fp32", pk_prior=prior)
 
-        def alternate(n, smp=smp):
-            for i in range(n):
-                (smp.sweep if i % 2 == 0 else smp.mixing_sweep)(1)
+            def alternate(n, smp=smp):
+                for i in range(n):
+                    (smp.sweep if i % 2 == 0 else smp.mixing_sweep)(1)
 
-        step = {"gibbs": smp.sweep, "mixing": smp.mixing_sweep, "alternating": alternate}[kind]
-        step(burn)
-        smp.set_diagnostics(start=burn, thin=thin, trace_cap=cap)
-        stream = torch.cuda.current_stream()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record(stream)
-        step(args.steps)
-        stop.record(stream)
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop) / args.steps
-        trace = smp.trace()
-        max_lag = min(cap - 1, 400)
-        _, nc = binding.acf(trace, max_lag)
-        mean_pk = trace.mean(dim=0).cpu().numpy()
-        ncv = nc.cpu().numpy()
-        out_runs[kind] = {"sweeps_per_s": round(1000.0 / ms, 1),
-                          "n_c_recorded": [int(v) for v in ncv],
-                          "bins_with_n_c_le_50": int(np.sum((ncv >= 0) & (ncv <= 50))),
-                          "posterior_mean_over_truth": [round(float(v), 3)
-                                                        for v in mean_pk / truth]}
-        smp.close()
-    best = max(out_runs, key=lambda k: out_runs[k]["bins_with_n_c_le_50"])
+            step = {"gibbs": smp.sweep, "mixing": smp.mixing_sweep, "alternating": alternate}[kind]
+            step(burn)
+            smp.set_diagnostics(start=burn, thin=thin, trace_cap=cap)
+            stream = torch.cuda.current_stream()
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            start.record(stream)
+            step(args.steps)
+            stop.record(stream)
+            torch.cuda.synchronize()
+            ms = start.elapsed_time(stop) / args.steps
+            trace = smp.trace()
+            max_lag = min(cap - 1, 400)
+            _, nc = binding.acf(trace, max_lag)
+            mean_pk = trace.mean(dim=0).cpu().numpy()
+            ncv = nc.cpu().numpy()
+            out_runs[kind] = {"sweeps_per_s": round(1000.0 / ms, 1),
+                              "n_c_recorded": [int(v) for v in ncv],
+                              "bins_with_n_c_le_50": int(np.sum((ncv >= 0) & (ncv <= 50))),
+                              "posterior_mean_over_truth": [round(float(v), 3)
+                                                            for v in mean_pk / truth]}
+            smp.close()
+        runs[prior_name] = out_runs
+    jeff = runs["jeffreys"]
+    best = max(jeff, key=lambda k: jeff[k]["bins_with_n_c_le_50"])
     out = {
         "metric": "share of P(k) bins with correlation length n_c <= 50 recorded samples "
                   "(ten-percent rule, every 10th sweep) at 128^3 FP32",
-        "value": round(out_runs[best]["bins_with_n_c_le_50"] / w.n_bins, 4),
+        "value": round(jeff[best]["bins_with_n_c_le_50"] / w.n_bins, 4),
         "unit": "fraction of bins", "n_gpus": 1, "steps": args.steps, "warmup": burn,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "chain-efficiency-128^3-fp32-survey", "thin": thin,
                    "recorded": cap, "bins": w.n_bins, "max_lag": min(cap - 1, 400),
-                   "best_sampler": best, **out_runs},
+                   "best_sampler": best, **jeff,
+                   "invgamma_prior": {"a0": EFFICIENCY_PRIOR[0], "b0": EFFICIENCY_PRIOR[1],
+                                      **runs["invgamma"]}},
     }
     print(json.dumps(out), flush=True)
 
@@ -551,7 +582,7 @@ def main():
     smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
                           seed=w.rng_seed, precision=w.precision)
     stream = torch.cuda.current_stream()
-    tune = smp.autotune(trials=20)      # set-up: picks the x-transform path, chain unchanged
+    tune = smp.autotune(trials=30)      # set-up: picks the path and tiles, chain unchanged
     # set-up: the chain's burn-in, which also takes the GPU from its idle clock
     # (about 180 MHz) to its steady one before anything is timed
     smp.sweep(args.burn_in)
@@ -600,9 +631,11 @@ def main():
         # the same kernels started with the 256 MB last-level cache evicted
         # (a 1 GiB copy before each timed kernel): their inputs come from DRAM
         evict = torch.empty(2 ** 30, dtype=torch.uint8, device="cuda")
-        kms_cold = smp.sweep_timed_cold(400, evict)
+        cold_modes = {mode: dict(zip(binding.KERNEL_NAMES,
+                                     [float(x) for x in smp.sweep_timed_cold(400, evict, mode)]))
+                      for mode in binding.Sampler.EVICT_MODES}
         del evict
-        cold_ms = dict(zip(binding.KERNEL_NAMES, [float(x) for x in kms_cold]))
+        cold_ms = cold_modes["read"]
         dom = max(kernel_ms, key=kernel_ms.get)
         achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
         traffic = load_traffic(dom, w.name)
@@ -623,7 +656,9 @@ def main():
                         k: round(alg[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                         for k, v in cold_ms.items()},
                     "llc_time_saving": {k: round(1.0 - kernel_ms[k] / cold_ms[k], 4)
-                                        for k in kernel_ms}}
+                                        for k in kernel_ms},
+                    "kernel_ms_llc_evicted_by_mode": {
+                        m: {k: round(v, 5) for k, v in d.items()} for m, d in cold_modes.items()}}
     smp.close()
     fp64 = None if args.no_fp64_compare else fp64_sweep_rate(w, pb, min(args.steps, 100))
     stream_ref = hbm_reference()
@@ -646,7 +681,11 @@ def main():
                    "mask": "sphere r<0.45L minus seeded 30deg wedge",
                    "chains": 1,
                    "x_path": tune["path"],
-                   "autotune_ms_per_sweep": {k: round(v, 5) for k, v in tune["ms"].items()},
+                   "tuning": {k: tune[k] for k in ("x_tile", "y_group", "x_cols", "x_k1",
+                                                   "y_units")},
+                   "autotune_ms_per_sweep": {k: _r5(v) for k, v in tune["ms"].items()},
+                   "autotune_ms_x_tile": [_r5(v) for v in tune["ms_x_tile"]],
+                   "autotune_ms_y_group": [_r5(v) for v in tune["ms_y_group"]],
                    "sweep_bytes_algorithmic": sweep_bytes,
                    "sweep_hbm_frac": round(sweep_bytes / (ms_per_step * 1e-3) / 1e9
                                            / HBM_PEAK_GBS, 4),

@@ -147,19 +147,23 @@ mf_status mf_gibbs_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
 mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream,
                                double* kernel_ms, int32_t n_kernels);
 
-/* As mf_gibbs_sweep_timed, with every timed kernel preceded by a copy of the
- * first half of the caller's device buffer `evict` onto its second half.  A
- * buffer several times the device's last-level (fabric) cache, 256 MB on
- * MI355X, leaves that cache holding none of the kernel's data, so the times
- * are those of passes that find their inputs in DRAM only; the difference to
- * mf_gibbs_sweep_timed is what the cache gives each pass.  The copies are not
- * inside the timed intervals.  The chain advances as with mf_gibbs_sweep.
+/* As mf_gibbs_sweep_timed, with every timed kernel preceded by a stream
+ * through the caller's device buffer `evict` (contents overwritten):
+ * evict_mode 0 copies its first half onto its second half, 1 reads all of
+ * it, 2 does both, copy then read.  A buffer several times the device's
+ * last-level (fabric) cache, 256 MB on MI355X, leaves that cache holding none
+ * of the kernel's data, so the times are those of passes that find their
+ * inputs in DRAM only; the difference to mf_gibbs_sweep_timed is what the
+ * cache gives each pass.  A copy leaves the cache full of dirty lines, whose
+ * write-back may then fall inside the timed kernel; a read leaves clean
+ * lines, if the cache allocates on reads.  The streams are not inside the
+ * timed intervals.  The chain advances as with mf_gibbs_sweep.
  * Errors: as mf_gibbs_sweep_timed, and MF_E_INVALID_ARG for an eviction
  * buffer that is NULL, not 16-byte aligned, not a multiple of 32 bytes or
- * smaller than 64 MiB. */
+ * smaller than 64 MiB, or a mode outside 0..2. */
 mf_status mf_gibbs_sweep_timed_cold(mf_problem* p, int32_t n_sweeps, void* stream,
                                     double* kernel_ms, int32_t n_kernels, void* evict,
-                                    size_t evict_bytes);
+                                    size_t evict_bytes, int32_t evict_mode);
 
 /* Copy chain `chain`'s state to the host: s_out (M doubles, may be NULL),
  * pk_out (n_bins doubles, physical units, may be NULL), sweep_out (number of
@@ -212,25 +216,54 @@ mf_status mf_load_checkpoint(mf_problem* p, int32_t chain, const void* buf, size
  * MF_E_DEVICE. */
 mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
 
-/* How Gibbs sweeps run the x transform, and its autotuner.
+/* How Gibbs sweeps run the transforms, and their autotuner.
  * Path 0 (split, 32 <= N <= 256): the y-passes also run the radix-N/16 half
  * of the x-DFT, and the x-pass runs 16-point DFTs in registers.
  * Path 1 (whole): the x-pass runs whole x pencils through LDS.  It is the
  * only path for N = 8, 16, 512.
- * Both paths give the same chain up to rounding and leave the same state
- * between sweeps, so they may be switched at any time.  The default is the
- * split path where it exists.  Mixing sweeps and the Wiener filter always
- * use the split path.
+ * On the split path two tile choices are open, three variants each:
+ *  - x_tile: the x-pass workgroup's iy columns and k1 values (variant 0 is
+ *    the library's rule; 1 and 2 are alternatives fixed per grid side, e.g.
+ *    at 256: 128 x 2, 64 x 4, and 128 x 2 without the occupancy bound);
+ *  - y_group: (kz, q) units per y-pass workgroup, the rule's G, G/2, G/4
+ *    (at least 1).
+ * Every choice gives the same chain up to rounding (the shell sums are
+ * grouped by workgroup) and leaves the same state between sweeps, so choices
+ * may change at any time.  The default is the split path with variants 0
+ * where it exists.  Mixing sweeps and the Wiener filter always use the split
+ * path with x-tile variant 0.
  * mf_set_x_path: MF_E_UNSUPPORTED_SIZE for the split path outside 32..256.
- * mf_autotune: times `trials` Gibbs sweeps of the problem on each available
- * path (after one warm-up sweep each) and selects the faster.  ms[path]
- * receives the mean sweep time in ms, NaN for a path not available.  Every
- * chain's state (spectrum, P, sweep index) is saved to host memory first and
- * restored bitwise afterwards.  Diagnostic recording is suspended meanwhile.
+ * mf_set_tuning / mf_get_tuning: the path and both variants at once;
+ *   mf_get_tuning also fills the geometry they stand for.  MF_E_INVALID_ARG
+ *   for a variant outside 0..2, MF_E_UNSUPPORTED_SIZE as mf_set_x_path.
+ * mf_autotune: coordinate search over the split path's x tiles (y group 0),
+ * then its y groups (with the best x tile), then that tuned split path
+ * against the whole-pencil path.  Each stage times its candidates in turn,
+ * three rounds of `trials` Gibbs sweeps each (after one warm-up sweep, and a
+ * warm-up of the device first), and keeps every candidate's fastest round;
+ * an alternative replaces the first candidate of its stage (the incumbent)
+ * only if faster by more than 1%.  ms (host, MF_TUNE_SLOTS doubles) receives
+ * the mean sweep time in ms of every candidate: [0] the tuned split path,
+ * [1] whole, [2 + v] x tile v, [5 + v] y group v, NaN for a candidate not
+ * available or equal to another.  picked (may be NULL)
+ * receives the choice as mf_get_tuning gives it.  Every chain's state
+ * (spectrum, P, sweep index) is saved to host memory first and restored
+ * bitwise afterwards.  Diagnostic recording is suspended meanwhile.
  * Synchronises `stream`. */
+typedef struct {
+  int32_t x_path;   /* 0 split, 1 whole */
+  int32_t x_tile;   /* split x-pass tile variant, 0..2 */
+  int32_t y_group;  /* split y-pass workgroup variant, 0..2 */
+  int32_t x_cols;   /* out (mf_get_tuning): iy columns per x-pass workgroup */
+  int32_t x_k1;     /* out: k1 values per split x-pass workgroup */
+  int32_t y_units;  /* out: (kz, q) units per split y-pass workgroup */
+} mf_tuning;
+#define MF_TUNE_SLOTS 8
 mf_status mf_set_x_path(mf_problem* p, int32_t path);
 mf_status mf_get_x_path(const mf_problem* p, int32_t* path);
-mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, int32_t* path_out);
+mf_status mf_set_tuning(mf_problem* p, const mf_tuning* t);
+mf_status mf_get_tuning(const mf_problem* p, mf_tuning* t);
+mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, mf_tuning* picked);
 
 /* Algorithmic HBM bytes of one sweep, per kernel (bytes[MF_NUM_KERNELS], in
  * sweep order), summed over the problem's chains.  Each pass reads and

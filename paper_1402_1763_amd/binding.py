@@ -52,6 +52,19 @@ class mf_chain_desc(ctypes.Structure):
     ]
 
 
+class mf_tuning(ctypes.Structure):
+    _fields_ = [
+        ("x_path", ctypes.c_int32),
+        ("x_tile", ctypes.c_int32),
+        ("y_group", ctypes.c_int32),
+        ("x_cols", ctypes.c_int32),
+        ("x_k1", ctypes.c_int32),
+        ("y_units", ctypes.c_int32),
+    ]
+
+
+MF_TUNE_SLOTS = 8
+
 SIGNATURES = {
     "mf_supported_n": (ctypes.c_int32, [ctypes.c_int32]),
     "mf_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(mf_chain_desc),
@@ -66,7 +79,8 @@ SIGNATURES = {
                                             _c_double_p, ctypes.c_int32]),
     "mf_gibbs_sweep_timed_cold": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                                  ctypes.c_void_p, _c_double_p, ctypes.c_int32,
-                                                 ctypes.c_void_p, ctypes.c_size_t]),
+                                                 ctypes.c_void_p, ctypes.c_size_t,
+                                                 ctypes.c_int32]),
     "mf_get_chain_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
                                           _c_double_p, ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.c_void_p]),
@@ -77,7 +91,9 @@ SIGNATURES = {
     "mf_set_x_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mf_get_x_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "mf_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, _c_double_p,
-                                   ctypes.POINTER(ctypes.c_int32)]),
+                                   ctypes.POINTER(mf_tuning)]),
+    "mf_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mf_tuning)]),
+    "mf_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mf_tuning)]),
     "mf_debug_run_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
                                            ctypes.c_void_p]),
     "mf_debug_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _c_double_p,
@@ -395,15 +411,19 @@ class Sampler:
     def sweep_timed(self, n_sweeps: int) -> np.ndarray:
         return mf_gibbs_sweep_timed(self.handle, n_sweeps, self.stream.cuda_stream)
 
-    def sweep_timed_cold(self, n_sweeps: int, evict) -> np.ndarray:
+    EVICT_MODES = ("copy", "read", "copy_read")
+
+    def sweep_timed_cold(self, n_sweeps: int, evict, mode: str = "read") -> np.ndarray:
         """Per-kernel mean ms, every timed kernel started after `evict` (a cuda
-        tensor far larger than the last-level cache) was streamed through."""
+        tensor far larger than the last-level cache) was streamed through
+        (copied, read, or both)."""
         out = np.zeros(MF_NUM_KERNELS, dtype=np.float64)
         nbytes = evict.numel() * evict.element_size() // 32 * 32
         _check(load().mf_gibbs_sweep_timed_cold(ctypes.c_void_p(self.handle), n_sweeps,
                                                 ctypes.c_void_p(self.stream.cuda_stream),
                                                 _dptr(out), MF_NUM_KERNELS,
-                                                ctypes.c_void_p(evict.data_ptr()), nbytes))
+                                                ctypes.c_void_p(evict.data_ptr()), nbytes,
+                                                self.EVICT_MODES.index(mode)))
         return out
 
     def state(self, chain: int = 0, want_s: bool = True):
@@ -423,14 +443,31 @@ class Sampler:
         _check(load().mf_get_x_path(ctypes.c_void_p(self.handle), ctypes.byref(out)))
         return self.X_PATHS[out.value]
 
+    def tuning(self) -> dict:
+        """The path, the split-path tile variants and the geometry they stand for."""
+        t = mf_tuning()
+        _check(load().mf_get_tuning(ctypes.c_void_p(self.handle), ctypes.byref(t)))
+        return {"path": self.X_PATHS[t.x_path], "x_tile": t.x_tile, "y_group": t.y_group,
+                "x_cols": t.x_cols, "x_k1": t.x_k1, "y_units": t.y_units}
+
+    def set_tuning(self, path: str = "split", x_tile: int = 0, y_group: int = 0):
+        t = mf_tuning(x_path=self.X_PATHS.index(path), x_tile=x_tile, y_group=y_group)
+        _check(load().mf_set_tuning(ctypes.c_void_p(self.handle), ctypes.byref(t)))
+
     def autotune(self, trials: int = 20) -> dict:
-        """Time both x-transform paths and keep the faster; returns
-        {"path": ..., "ms": {"split": ..., "whole": ...}} (state unchanged)."""
-        ms = (ctypes.c_double * 2)()
-        path = ctypes.c_int32(0)
+        """Search the x path and the split path's tile variants and keep the
+        fastest; returns the pick (as tuning()) with the timings:
+        "ms" {"split", "whole"}, "ms_x_tile" [3], "ms_y_group" [3] (NaN where
+        a candidate is not available or equals another).  State unchanged."""
+        ms = (ctypes.c_double * MF_TUNE_SLOTS)()
+        t = mf_tuning()
         _check(load().mf_autotune(ctypes.c_void_p(self.handle), trials,
-                                  ctypes.c_void_p(self.stream.cuda_stream), ms, ctypes.byref(path)))
-        return {"path": self.X_PATHS[path.value], "ms": dict(zip(self.X_PATHS, list(ms)))}
+                                  ctypes.c_void_p(self.stream.cuda_stream), ms, ctypes.byref(t)))
+        out = self.tuning()
+        out["ms"] = {"split": ms[0], "whole": ms[1]}
+        out["ms_x_tile"] = [ms[2], ms[3], ms[4]]
+        out["ms_y_group"] = [ms[5], ms[6], ms[7]]
+        return out
 
     def sweep_bytes(self) -> dict:
         """Algorithmic HBM bytes of one sweep per kernel (all chains)."""

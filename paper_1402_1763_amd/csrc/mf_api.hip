@@ -59,42 +59,72 @@ bool supported(int n) {
 // Both leave the same state between sweeps, so a problem may switch.
 enum XPath : int { kPathSplit = 0, kPathWhole = 1 };
 
+// Tile variants of the split path searched by the autotuner: x-pass tiles
+// (XSTile<R, N, V>) and y-pass workgroup sizes (YSTile<R, N, V>).
+constexpr int kTileVariants = 3;
+
 template <typename R, int N>
 struct Geometry {
+  template <int V>
   static constexpr int split_wpp() {
-    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N>::WPP;
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::WPP;
     else return N / mf::XTile<R, N>::P;
   }
-  static constexpr int xp_split = split_wpp();
+  template <int V>
+  static constexpr int y_units() {
+    if constexpr (mf::split_x<N>()) return mf::YSTile<R, N, V>::G;
+    else return 0;
+  }
+  template <int V>
+  static constexpr int x_cols() {
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::P;
+    else return 0;
+  }
+  template <int V>
+  static constexpr int x_k1() {
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::K1;
+    else return 0;
+  }
   static constexpr int xp_whole = N / mf::XTile<R, N>::P;
   static constexpr int ztiles = (N / mf::ZTile<R, N>::IXB) * (N / mf::ZTile<R, N>::P);
   static constexpr int zept = mf::ZTile<R, N>::EPT;
 };
 
 struct Shape {
-  int xp_split, xp_whole;   // x-pass workgroups per kz plane on each path
-  int ztiles;               // z-pass tiles per chain
-  int zept;                 // elements per z-pass lane (observation bits per tile)
+  int xp_split[kTileVariants];   // split x-pass workgroups per kz plane, per tile variant
+  int x_cols[kTileVariants];     // their iy columns and k1 values per workgroup
+  int x_k1[kTileVariants];
+  int y_units[kTileVariants];    // (kz, q) units per split y-pass workgroup, per variant
+  int xp_whole;                  // whole-pencil x-pass workgroups per kz plane
+  int ztiles;                    // z-pass tiles per chain
+  int zept;                      // elements per z-pass lane (observation bits per tile)
 };
 
 template <typename R>
 Shape shape_of(int n) {
   switch (n) {
-#define MF_SHAPE(NN) \
-  case NN: return Shape{Geometry<R, NN>::xp_split, Geometry<R, NN>::xp_whole, Geometry<R, NN>::ztiles, \
-                        Geometry<R, NN>::zept};
+#define MF_SHAPE(NN)                                                                       \
+  case NN: {                                                                               \
+    using G = Geometry<R, NN>;                                                             \
+    return Shape{{G::template split_wpp<0>(), G::template split_wpp<1>(), G::template split_wpp<2>()}, \
+                 {G::template x_cols<0>(), G::template x_cols<1>(), G::template x_cols<2>()},   \
+                 {G::template x_k1<0>(), G::template x_k1<1>(), G::template x_k1<2>()},         \
+                 {G::template y_units<0>(), G::template y_units<1>(), G::template y_units<2>()}, \
+                 G::xp_whole, G::ztiles, G::zept};                                         \
+  }
     MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(48) MF_SHAPE(64) MF_SHAPE(80) MF_SHAPE(96)
     MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
 #undef MF_SHAPE
   }
-  return Shape{0, 0, 0};
+  return Shape{};
 }
 
 struct Layout {
   size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, tobs, coef, spec, staging,
       rinv, total;
   size_t spec_elems, spec_stride;
-  int n_wg_split, n_wg_whole;   // x-pass workgroups (one shell partial each) per path
+  int n_wg_split[kTileVariants];   // split x-pass workgroups (one shell partial each) per variant
+  int n_wg_whole;                  // whole-pencil x-pass workgroups
   int n_wg_max;
 };
 
@@ -106,9 +136,12 @@ Layout make_layout(const mf_chain_desc& d) {
   Layout L{};
   L.spec_elems = (n / 2 + 1) * n * n;
   L.spec_stride = align_up(L.spec_elems * 2 * rs) / (2 * rs);
-  L.n_wg_split = static_cast<int>((n / 2 + 1) * sh.xp_split);
   L.n_wg_whole = static_cast<int>((n / 2 + 1) * sh.xp_whole);
-  L.n_wg_max = std::max(L.n_wg_split, L.n_wg_whole);
+  L.n_wg_max = L.n_wg_whole;
+  for (int v = 0; v < kTileVariants; ++v) {
+    L.n_wg_split[v] = static_cast<int>((n / 2 + 1) * sh.xp_split[v]);
+    L.n_wg_max = std::max(L.n_wg_max, L.n_wg_split[v]);
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -232,16 +265,21 @@ struct mf_problem {
   DiagRec diag;
   std::vector<int> obs_chunks;  // per chain: z-pass (tile, element) chunks holding an observed voxel
   int xpath;                    // XPath of Gibbs sweeps
+  int xvar = 0, yvar = 0;       // split-path tile variants of Gibbs sweeps (autotuner)
   int graphs = 0;               // live graphs that captured this problem's sweep
-  int n_wg(int path) const { return path == kPathSplit ? L.n_wg_split : L.n_wg_whole; }
+  // x-pass workgroups of a path; the split path's with x-tile variant xv
+  int n_wg(int path, int xv) const { return path == kPathSplit ? L.n_wg_split[xv] : L.n_wg_whole; }
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
 
 namespace {
 
+// Sweep arguments with the x-pass on `path` (< 0: the problem's Gibbs path)
+// and split x-tile variant xv (< 0: the problem's Gibbs variant).
 template <typename R>
-mf::SweepArgs<R> args_of(const mf_problem* p, int path = -1) {
+mf::SweepArgs<R> args_of(const mf_problem* p, int path = -1, int xv = -1) {
   if (path < 0) path = p->xpath;
+  if (xv < 0) xv = p->xvar;
   mf::SweepArgs<R> a{};
   char* ws = p->ws;
   a.spec = reinterpret_cast<mf::cx<R>*>(ws + p->L.spec);
@@ -263,7 +301,7 @@ mf::SweepArgs<R> args_of(const mf_problem* p, int path = -1) {
   a.spec_stride = p->L.spec_stride;
   a.m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
   a.nb = p->desc.n_bins;
-  a.n_wg_x = p->n_wg(path);
+  a.n_wg_x = p->n_wg(path, xv);
   a.staging_chain = 0;
   a.sample_pk = p->desc.sample_pk;
   a.chain0 = p->desc.chain_id;
@@ -289,12 +327,32 @@ enum KernelId {
   kZDetK = 13, kZAccK = 14, kXDetK = 15, kXAdjK = 16, kXMixK = 17, kMixPkK = 18, kXMixInvK = 19
 };
 
+// Split-path y-pass with units variant V.
+template <typename R, int N, bool INV, int V>
+void launch_ysplit(const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
+  using YS = mf::YSTile<R, N, V>;
+  const int extra = INV ? a.nb : 0;   // the P(k) workgroups
+  hipLaunchKernelGGL((mf::ysplit_kernel<R, N, INV, V>), dim3(16 / YS::G * (N / 2 + 1) + extra, 1, nch),
+                     dim3(YS::NT), 0, st, a);
+}
+
+// Split-path Gibbs x-pass with tile variant V.
+template <typename R, int N, int V>
+void launch_xsplit(const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
+  using XS = mf::XSTile<R, N, V>;
+  const size_t tables = 2 * a.nb * sizeof(R) + (a.nb + 1) * 4;
+  hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample, V>), dim3(XS::WPP, N / 2 + 1, nch),
+                     dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+}
+
+// xv, yv: split-path tile variants of the Gibbs x-pass and of the y-passes;
+// every other kernel runs variant 0.
 template <typename R, int N>
-void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool whole) {
+void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool whole, int xv,
+              int yv) {
   using ZT = mf::ZTile<R, N>;
   using YT = mf::YTile<R, N>;
   using XT = mf::XTile<R, N>;
-  using YS = mf::YSTile<R, N>;
   using XS = mf::XSTile<R, N>;
   constexpr bool can_split = mf::split_x<N>();
   const bool split = can_split && !whole;
@@ -319,8 +377,9 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
     case kYF:
       if constexpr (can_split) {
         if (split) {
-          hipLaunchKernelGGL((mf::ysplit_kernel<R, N, false>), dim3(16 / YS::G * (N / 2 + 1), 1, nch),
-                             dim3(YS::NT), 0, st, a);
+          if (yv == 1) launch_ysplit<R, N, false, 1>(a, nch, st);
+          else if (yv == 2) launch_ysplit<R, N, false, 2>(a, nch, st);
+          else launch_ysplit<R, N, false, 0>(a, nch, st);
           break;
         }
       }
@@ -330,8 +389,9 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
     case kYI:
       if constexpr (can_split) {
         if (split) {
-          hipLaunchKernelGGL((mf::ysplit_kernel<R, N, true>),
-                             dim3(16 / YS::G * (N / 2 + 1) + a.nb, 1, nch), dim3(YS::NT), 0, st, a);
+          if (yv == 1) launch_ysplit<R, N, true, 1>(a, nch, st);
+          else if (yv == 2) launch_ysplit<R, N, true, 2>(a, nch, st);
+          else launch_ysplit<R, N, true, 0>(a, nch, st);
           break;
         }
       }
@@ -364,8 +424,9 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
     case kX:
       if constexpr (can_split) {
         if (split) {
-          hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample>), dim3(XS::WPP, N / 2 + 1, nch),
-                             dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+          if (xv == 1) launch_xsplit<R, N, 1>(a, nch, st);
+          else if (xv == 2) launch_xsplit<R, N, 2>(a, nch, st);
+          else launch_xsplit<R, N, 0>(a, nch, st);
           break;
         }
       }
@@ -379,36 +440,39 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
 }
 
 template <typename R>
-void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st, bool whole = false) {
+void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st, bool whole = false,
+            int xv = 0, int yv = 0) {
   switch (n) {
-    case 8: launch_n<R, 8>(id, a, nch, st, whole); break;
-    case 16: launch_n<R, 16>(id, a, nch, st, whole); break;
-    case 32: launch_n<R, 32>(id, a, nch, st, whole); break;
-    case 48: launch_n<R, 48>(id, a, nch, st, whole); break;
-    case 64: launch_n<R, 64>(id, a, nch, st, whole); break;
-    case 80: launch_n<R, 80>(id, a, nch, st, whole); break;
-    case 96: launch_n<R, 96>(id, a, nch, st, whole); break;
-    case 128: launch_n<R, 128>(id, a, nch, st, whole); break;
-    case 256: launch_n<R, 256>(id, a, nch, st, whole); break;
-    case 512: launch_n<R, 512>(id, a, nch, st, whole); break;
+    case 8: launch_n<R, 8>(id, a, nch, st, whole, xv, yv); break;
+    case 16: launch_n<R, 16>(id, a, nch, st, whole, xv, yv); break;
+    case 32: launch_n<R, 32>(id, a, nch, st, whole, xv, yv); break;
+    case 48: launch_n<R, 48>(id, a, nch, st, whole, xv, yv); break;
+    case 64: launch_n<R, 64>(id, a, nch, st, whole, xv, yv); break;
+    case 80: launch_n<R, 80>(id, a, nch, st, whole, xv, yv); break;
+    case 96: launch_n<R, 96>(id, a, nch, st, whole, xv, yv); break;
+    case 128: launch_n<R, 128>(id, a, nch, st, whole, xv, yv); break;
+    case 256: launch_n<R, 256>(id, a, nch, st, whole, xv, yv); break;
+    case 512: launch_n<R, 512>(id, a, nch, st, whole, xv, yv); break;
   }
 }
 
-// path < 0: the problem's Gibbs-sweep path.
+// path < 0: the problem's Gibbs-sweep path and tile variants; a given path
+// (the mixing sweep's split path) runs tile variant 0 of the x-pass.
 mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t st, int path = -1,
                          int pk_mode = mf::kPkDraw) {
   const int nch = p->desc.n_chains;
+  const int xv = path < 0 ? p->xvar : 0, yv = p->yvar;
   if (path < 0) path = p->xpath;
   if (p->fp64()) {
-    auto a = args_of<double>(p, path);
+    auto a = args_of<double>(p, path, xv);
     a.staging_chain = staging_chain;
     a.pk_mode = pk_mode;
-    launch<double>(id, a, p->desc.n, nch, st, path == kPathWhole);
+    launch<double>(id, a, p->desc.n, nch, st, path == kPathWhole, xv, yv);
   } else {
-    auto a = args_of<float>(p, path);
+    auto a = args_of<float>(p, path, xv);
     a.staging_chain = staging_chain;
     a.pk_mode = pk_mode;
-    launch<float>(id, a, p->desc.n, nch, st, path == kPathWhole);
+    launch<float>(id, a, p->desc.n, nch, st, path == kPathWhole, xv, yv);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MF_E_DEVICE, "kernel %d launch failed: %s", id, hipGetErrorString(e));
@@ -762,11 +826,12 @@ namespace {
 // Gibbs sweeps with kernel i mod MF_NUM_KERNELS of sweep i timed by one pair
 // of events that skip the system-scope fence (a cache write-back and
 // invalidate at every event would slow the kernels being timed).  With an
-// eviction buffer, its first half is copied onto its second half just before
-// each timed kernel, so that the kernel starts with the fabric's last-level
-// cache holding none of its data.
+// eviction buffer, it is streamed through just before each timed kernel, so
+// that the kernel starts with the fabric's last-level cache holding none of
+// its data: mode 0 copies its first half onto its second half, mode 1 reads
+// all of it, mode 2 does both (copy, then read).
 mf_status timed_sweeps(mf_problem* p, int32_t n_sweeps, hipStream_t hs, double* kernel_ms,
-                       int32_t n_kernels, void* evict, size_t evict_bytes) {
+                       int32_t n_kernels, void* evict, size_t evict_bytes, int evict_mode) {
   if (!p || !kernel_ms || n_kernels < 0) return fail(MF_E_INVALID_ARG, "bad argument");
   if (n_sweeps <= 0) return fail(MF_E_INVALID_ARG, "need at least one sweep");
   const mf_status room = check_sweep_room(p, n_sweeps);
@@ -780,8 +845,12 @@ mf_status timed_sweeps(mf_problem* p, int32_t n_sweeps, hipStream_t hs, double* 
     for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k) {
       if (k == timed && evict) {
         const auto* src = static_cast<const mf::v4u*>(evict);
-        hipLaunchKernelGGL(mf::stream_copy_kernel<false>, dim3(16384), dim3(mf::kStreamThreads),
-                           0, hs, src, static_cast<mf::v4u*>(evict) + half16, half16);
+        if (evict_mode != 1)
+          hipLaunchKernelGGL(mf::stream_copy_kernel<false>, dim3(16384), dim3(mf::kStreamThreads),
+                             0, hs, src, static_cast<mf::v4u*>(evict) + half16, half16);
+        if (evict_mode != 0)   // one sum per workgroup lands in the buffer's first 16 KiB
+          hipLaunchKernelGGL(mf::stream_read_kernel<false>, dim3(4096), dim3(mf::kStreamThreads),
+                             0, hs, src + 1024, static_cast<uint32_t*>(evict), 2 * half16 - 1024);
       }
       if (k == timed) MF_HIP(hipEventRecord(ev[2 * i], hs));
       st = launch_checked(p, kSweepOrder[k], 0, hs);
@@ -813,18 +882,19 @@ extern "C" {
 mf_status mf_gibbs_sweep_timed(mf_problem* p, int32_t n_sweeps, void* stream, double* kernel_ms,
                                int32_t n_kernels) {
   return timed_sweeps(p, n_sweeps, static_cast<hipStream_t>(stream), kernel_ms, n_kernels,
-                      nullptr, 0);
+                      nullptr, 0, 0);
 }
 
 mf_status mf_gibbs_sweep_timed_cold(mf_problem* p, int32_t n_sweeps, void* stream,
                                     double* kernel_ms, int32_t n_kernels, void* evict,
-                                    size_t evict_bytes) {
+                                    size_t evict_bytes, int32_t evict_mode) {
   if (!evict || reinterpret_cast<uintptr_t>(evict) % 16 != 0 || evict_bytes < (64u << 20) ||
       evict_bytes % 32 != 0)
     return fail(MF_E_INVALID_ARG, "eviction buffer: 16-byte aligned, a multiple of 32 bytes, "
                 "at least 64 MiB");
+  if (evict_mode < 0 || evict_mode > 2) return fail(MF_E_INVALID_ARG, "evict_mode %d outside 0..2", evict_mode);
   return timed_sweeps(p, n_sweeps, static_cast<hipStream_t>(stream), kernel_ms, n_kernels,
-                      evict, evict_bytes);
+                      evict, evict_bytes, evict_mode);
 }
 
 mf_status mf_get_chain_state(mf_problem* p, int32_t chain, double* s_out, double* pk_out,
@@ -953,64 +1023,152 @@ mf_status mf_get_x_path(const mf_problem* p, int32_t* path) {
   return MF_OK;
 }
 
-mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, int32_t* path_out) {
-  if (!p || !ms || !path_out) return fail(MF_E_INVALID_ARG, "NULL argument");
-  if (trials < 1) return fail(MF_E_INVALID_ARG, "need at least one trial sweep");
+mf_status mf_set_tuning(mf_problem* p, const mf_tuning* t) {
+  if (!p || !t) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (t->x_tile < 0 || t->x_tile >= kTileVariants || t->y_group < 0 || t->y_group >= kTileVariants)
+    return fail(MF_E_INVALID_ARG, "tile variants must be 0..%d", kTileVariants - 1);
+  const mf_status st = mf_set_x_path(p, t->x_path);
+  if (st != MF_OK) return st;
+  p->xvar = t->x_tile;
+  p->yvar = t->y_group;
+  return MF_OK;
+}
+
+mf_status mf_get_tuning(const mf_problem* p, mf_tuning* t) {
+  if (!p || !t) return fail(MF_E_INVALID_ARG, "NULL argument");
+  t->x_path = p->xpath;
+  t->x_tile = p->xvar;
+  t->y_group = p->yvar;
+  const bool split = p->xpath == kPathSplit;
+  t->x_cols = split ? p->sh.x_cols[p->xvar] : 0;
+  t->x_k1 = split ? p->sh.x_k1[p->xvar] : 0;
+  t->y_units = split ? p->sh.y_units[p->yvar] : 0;
+  return MF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Mean ms of `trials` Gibbs sweeps (after one warm-up sweep) with the given
+// choices; restores nothing (the caller saved the chains).
+mf_status time_choice(mf_problem* p, int path, int xv, int yv, int trials, void* stream,
+                      hipEvent_t e0, hipEvent_t e1, double* ms) {
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  ms[kPathSplit] = ms[kPathWhole] = std::numeric_limits<double>::quiet_NaN();
+  p->xpath = path;
+  p->xvar = xv;
+  p->yvar = yv;
+  mf_status st = mf_gibbs_sweep(p, 1, stream);
+  if (st != MF_OK) return st;
+  MF_HIP(hipEventRecord(e0, hs));
+  if ((st = mf_gibbs_sweep(p, trials, stream)) != MF_OK) return st;
+  MF_HIP(hipEventRecord(e1, hs));
+  MF_HIP(hipEventSynchronize(e1));
+  float t = 0.f;
+  MF_HIP(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / trials;
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Rounds of the autotuner's search: each stage times its candidates in turn,
+// this many times, and keeps every candidate's fastest round; an alternative
+// replaces the incumbent only when it is faster by more than kTuneMargin.
+constexpr int kTuneRounds = 3;
+constexpr double kTuneMargin = 0.01;
+
+mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, mf_tuning* picked) {
+  if (!p || !ms) return fail(MF_E_INVALID_ARG, "NULL argument");
+  if (trials < 1) return fail(MF_E_INVALID_ARG, "need at least one trial sweep");
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int i = 0; i < MF_TUNE_SLOTS; ++i) ms[i] = nan;
   const bool can_split = p->desc.n >= 32 && p->desc.n <= 256;
   if (!can_split) {
     p->xpath = kPathWhole;
-    *path_out = kPathWhole;
-    return MF_OK;
+    p->xvar = p->yvar = 0;
+    return picked ? mf_get_tuning(p, picked) : MF_OK;
   }
+  // every candidate's sweeps must fit below the 2^32 sweep-index bound; the
+  // chains are restored afterwards
+  const int warm = std::max<int>(trials, 20);
+  const int64_t budget = static_cast<int64_t>(kTuneRounds) * 8 * (trials + 1) + warm;
+  mf_status st = check_sweep_room(p, budget);
+  if (st != MF_OK) return st;
   // Save every chain (spectrum, P, sweep index) and switch recording off, so
   // the trial sweeps leave no trace.
   const size_t cb = checkpoint_bytes(p);
   std::vector<std::vector<char>> saved(p->desc.n_chains, std::vector<char>(cb));
-  mf_status st = MF_OK;
   for (int c = 0; c < p->desc.n_chains && st == MF_OK; ++c)
     st = mf_save_checkpoint(p, c, saved[c].data(), cb, stream);
   if (st != MF_OK) return st;
   const DiagRec diag = p->diag;
-  const int path0 = p->xpath;
+  const int path0 = p->xpath, xv0 = p->xvar, yv0 = p->yvar;
   p->diag = DiagRec{};
   hipEvent_t e0, e1;
   MF_HIP(hipEventCreate(&e0));
   MF_HIP(hipEventCreate(&e1));
-  for (int path : {kPathSplit, kPathWhole}) {
-    p->xpath = path;
-    if ((st = mf_gibbs_sweep(p, 1, stream)) != MF_OK) break;   // warm-up
-    (void)hipEventRecord(e0, hs);
-    if ((st = mf_gibbs_sweep(p, trials, stream)) != MF_OK) break;
-    (void)hipEventRecord(e1, hs);
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      st = fail(MF_E_DEVICE, "autotune timing failed");
-      break;
-    }
-    float t = 0.f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    ms[path] = t / trials;
-  }
+  // candidates of a stage: (path, x tile, y group, slot); fastest round kept
+  struct Cand { int path, xv, yv, slot; };
+  auto run_stage = [&](const std::vector<Cand>& cands) {
+    for (int r = 0; r < kTuneRounds && st == MF_OK; ++r)
+      for (const Cand& c : cands) {
+        double t = 0.0;
+        st = time_choice(p, c.path, c.xv, c.yv, trials, stream, e0, e1, &t);
+        if (st != MF_OK) return;
+        if (!(ms[c.slot] <= t)) ms[c.slot] = t;   // NaN or slower: replace
+      }
+  };
+  // index of the fastest candidate; the first (incumbent) wins ties and
+  // margins below kTuneMargin
+  auto pick = [&](const std::vector<Cand>& cands) {
+    int best = 0;
+    for (int i = 1; i < static_cast<int>(cands.size()); ++i)
+      if (ms[cands[i].slot] < ms[cands[best].slot] * (1.0 - kTuneMargin)) best = i;
+    return best;
+  };
+  p->xpath = kPathSplit;
+  p->xvar = p->yvar = 0;
+  st = mf_gibbs_sweep(p, warm, stream);   // device warm-up
+  // 1. x tiles on the split path, y group 0
+  std::vector<Cand> xs;
+  for (int v = 0; v < kTileVariants; ++v) xs.push_back({kPathSplit, v, 0, 2 + v});
+  run_stage(xs);
+  const int best_x = st == MF_OK ? xs[pick(xs)].xv : 0;
+  // 2. y groups with the best x tile (groups of equal size are timed once)
+  std::vector<Cand> ys{{kPathSplit, best_x, 0, 5}};
+  for (int v = 1; v < kTileVariants; ++v)
+    if (p->sh.y_units[v] != p->sh.y_units[v - 1]) ys.push_back({kPathSplit, best_x, v, 5 + v});
+  if (st == MF_OK) run_stage(ys);
+  const int best_y = st == MF_OK ? ys[pick(ys)].yv : 0;
+  // 3. the split path so tuned against the whole-pencil path
+  std::vector<Cand> paths{{kPathSplit, best_x, best_y, 0}, {kPathWhole, 0, 0, 1}};
+  if (st == MF_OK) run_stage(paths);
+  const bool whole = st == MF_OK && pick(paths) == 1;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p->diag = diag;
   p->xpath = path0;
+  p->xvar = xv0;
+  p->yvar = yv0;
   for (int c = 0; c < p->desc.n_chains; ++c) {
     const mf_status r = mf_load_checkpoint(p, c, saved[c].data(), cb, stream);
     if (st == MF_OK) st = r;
   }
   if (st != MF_OK) return st;
-  p->xpath = ms[kPathWhole] < ms[kPathSplit] ? kPathWhole : kPathSplit;
-  *path_out = p->xpath;
-  return MF_OK;
+  p->xpath = whole ? kPathWhole : kPathSplit;
+  p->xvar = whole ? 0 : best_x;
+  p->yvar = whole ? 0 : best_y;
+  return picked ? mf_get_tuning(p, picked) : MF_OK;
 }
 
 mf_status mf_sweep_bytes(const mf_problem* p, size_t* bytes) {
   if (!p || !bytes) return fail(MF_E_INVALID_ARG, "NULL argument");
   const size_t rs = p->fp64() ? 8 : 4, n = p->desc.n, m = n * n * n, nb = p->desc.n_bins;
   const size_t spec = (n / 2 + 1) * n * n * 2 * rs;
-  const size_t part = static_cast<size_t>(p->n_wg(p->xpath)) * nb * 8;
+  const size_t part = static_cast<size_t>(p->n_wg(p->xpath, p->xvar)) * nb * 8;
   for (int k = 0; k < MF_NUM_KERNELS; ++k) bytes[k] = 0;
   for (int c = 0; c < p->desc.n_chains; ++c) {
     const size_t coef = 2 * m * rs * static_cast<size_t>(p->obs_chunks[c]) / (p->sh.ztiles * p->sh.zept);
@@ -1246,7 +1404,7 @@ void with_n(int n, F&& f) {
 template <typename R>
 mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, const R* coef, R* table, double* pkg,
                              double* gacc) {
-  mf::SweepArgs<R> a = args_of<R>(p, kPathSplit);
+  mf::SweepArgs<R> a = args_of<R>(p, kPathSplit, 0);
   a.coef = coef;
   a.table = table;
   a.pk = pkg;

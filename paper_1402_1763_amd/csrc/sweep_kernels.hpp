@@ -663,8 +663,9 @@ __host__ __device__ constexpr bool split_x() { return N >= 32 && N <= 256; }
 // Forward y-pass with x stage A (INV = false), or inverse x stage A with the
 // inverse y-pass (INV = true, plus the P(k) step in the first nb workgroups).
 // Workgroup = G units (kz, q), q = q0 .. q0 + G - 1: each the NA y pencils of
-// rows ix = q + 16 r.
-template <typename R, int N>
+// rows ix = q + 16 r.  Variant V (searched by the autotuner) takes G0 / 2^V
+// units, G0 the rule below.
+template <typename R, int N, int V = 0>
 struct YSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
   static constexpr int EPT = ept<N>();
@@ -675,15 +676,16 @@ struct YSTile {
   // units per workgroup: up to 256 threads and 48 KB of LDS
   static constexpr int GCAP_T = 256 / TPU;
   static constexpr int GCAP_L = 49152 / (NA * PSTR * 2 * static_cast<int>(sizeof(R)));
-  static constexpr int G = pow2_divisor(16, GCAP_T < GCAP_L ? GCAP_T : GCAP_L);
+  static constexpr int G0 = pow2_divisor(16, GCAP_T < GCAP_L ? GCAP_T : GCAP_L);
+  static constexpr int G = (G0 >> V) > 0 ? (G0 >> V) : 1;
   static constexpr int NT = G * TPU;
   using TL = Tile<N, G * NA, NT, false, PSTR, PADS>;
 };
 
-template <typename R, int N, bool INV>
-__global__ void __launch_bounds__((YSTile<R, N>::NT))
+template <typename R, int N, bool INV, int V = 0>
+__global__ void __launch_bounds__((YSTile<R, N, V>::NT))
 ysplit_kernel(SweepArgs<R> a) {
-  using T = YSTile<R, N>;
+  using T = YSTile<R, N, V>;
   using TL = typename T::TL;
   constexpr int NA = T::NA, NT = T::NT, EPT = T::EPT, COLS = T::COLS, G = T::G, TPU = T::TPU;
   __shared__ cx<R> lds[G * NA * T::PSTR];
@@ -1021,13 +1023,31 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
 // HBM rewards: sides divisible by 64 with NA >= 4 take P = min(N, 128) (1 KiB
 // runs in FP32) and K1 = 256 / P, so NA / K1 workgroups share a column block.
 // At 256^3 that took the pass from 41.7 us (P = 16) to 36.7 us.  The other
-// sides take every k1 of a column.
-template <typename R, int N>
+// sides take every k1 of a column.  Variants 1 and 2 are the alternative
+// tiles the autotuner tries (xs_alt); variant 0 is this rule.
+//   (P, K1) of variants 1, 2 per side: 256: (64, 4), (128, 2) without the
+//   5-wave bound; 128: (64, 4), (32, 8); 96: (96, 2), (48, 6);
+//   80: (80, 1), (16, 5); 64: (64, 2), (32, 4); 48: (48, 1), (16, 3);
+//   32: (32, 1), (16, 2).
+__host__ __device__ constexpr int xs_alt(int n, int v, bool k1) {
+  switch (n) {
+    case 256: return v == 1 ? (k1 ? 4 : 64) : (k1 ? 2 : 128);
+    case 128: return v == 1 ? (k1 ? 4 : 64) : (k1 ? 8 : 32);
+    case 96: return v == 1 ? (k1 ? 2 : 96) : (k1 ? 6 : 48);
+    case 80: return v == 1 ? (k1 ? 1 : 80) : (k1 ? 5 : 16);
+    case 64: return v == 1 ? (k1 ? 2 : 64) : (k1 ? 4 : 32);
+    case 48: return v == 1 ? (k1 ? 1 : 48) : (k1 ? 3 : 16);
+    default: return v == 1 ? (k1 ? 1 : n) : (k1 ? 2 : 16);
+  }
+}
+
+template <typename R, int N, int V = 0>
 struct XSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
   static constexpr bool WIDE = N % 64 == 0 && NA >= 4 && NA % 4 == 0;
-  static constexpr int P = WIDE ? (N < 128 ? N : 128) : divisor_below(N, 256 / NA);   // columns per workgroup
-  static constexpr int K1 = WIDE ? 256 / P : NA;     // k1 values per workgroup
+  static constexpr int P0 = WIDE ? (N < 128 ? N : 128) : divisor_below(N, 256 / NA);
+  static constexpr int P = V == 0 ? P0 : xs_alt(N, V, false);          // columns per workgroup
+  static constexpr int K1 = V == 0 ? (WIDE ? 256 / P0 : NA) : xs_alt(N, V, true);   // k1 values
   static constexpr int KB = NA / K1;                 // workgroups per column block
   static constexpr int NT = P * K1;
   static constexpr int WPP = (N / P) * KB;           // workgroups per kz plane
@@ -1036,13 +1056,13 @@ struct XSTile {
   static_assert(N % P == 0 && NA % K1 == 0 && NT <= 1024, "x-pass tile must cover the plane");
   // FP32 at N = 256 would take 98 VGPRs (4 waves per SIMD); held to 96 (5
   // waves, no spill) the pass runs 33.2 us instead of 35.5 us.
-  static constexpr int MIN_WAVES = (sizeof(R) == 4 && N == 256) ? 5 : 1;
+  static constexpr int MIN_WAVES = (V == 0 && sizeof(R) == 4 && N == 256) ? 5 : 1;
 };
 
-template <typename R, int N, int XM>
-__global__ void __launch_bounds__((XSTile<R, N>::NT), (XSTile<R, N>::MIN_WAVES))
+template <typename R, int N, int XM, int V = 0>
+__global__ void __launch_bounds__((XSTile<R, N, V>::NT), (XSTile<R, N, V>::MIN_WAVES))
 xsplit_kernel(SweepArgs<R> a) {
-  using T = XSTile<R, N>;
+  using T = XSTile<R, N, V>;
   constexpr int P = T::P, NT = T::NT, NA = T::NA;
   extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb + 1)
   const int tid = threadIdx.x;

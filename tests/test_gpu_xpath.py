@@ -1,5 +1,5 @@
-"""GPU tests of the two x-transform paths (split and whole pencils) and of the
-autotuner that chooses between them."""
+"""GPU tests of the two x-transform paths (split and whole pencils), of the
+split path's tile variants, and of the autotuner that chooses among them."""
 import numpy as np
 import pytest
 
@@ -36,19 +36,58 @@ def test_whole_path_matches_oracle(precision, n):
     assert err_s < TOL[precision] and err_p < TOL[precision]
 
 
-def test_paths_agree_at_256():
+@pytest.mark.timeout(600)
+def test_every_path_and_tile_at_256_matches_oracle():
+    """The benchmarked 256^3 survey problem, 2 sweeps, on the whole-pencil path
+    and on the split path with each x-tile variant, against the oracle."""
     w = workloads.SURVEY_256_MIXED
     pb = workloads.make_problem(w)
-    out = []
-    for path in ("split", "whole"):
+    print("256^3: oracle 2 sweeps", flush=True)
+    s_ref, p_ref = run_oracle(w, pb, 2)
+    for path, x_tile in (("whole", 0), ("split", 0), ("split", 1), ("split", 2)):
         smp = gpu_sampler(w, pb)
-        smp.set_x_path(path)
+        smp.set_tuning(path, x_tile, 0)
         smp.sweep(2)
-        out.append(smp.state()[:2])
+        s_gpu, p_gpu, _ = smp.state()
+        geo = smp.tuning()
         smp.close()
-    err_s, err_p = errors(out[1][0], out[1][1], out[0][0], out[0][1])
-    print(f"256^3 split vs whole: err_s={err_s:.3e} err_P={err_p:.3e}", flush=True)
-    assert err_s < 2e-5 and err_p < 2e-5
+        err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+        print(f"  {path} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}): err_s={err_s:.3e} "
+              f"err_P={err_p:.3e}", flush=True)
+        assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
+
+
+@pytest.mark.parametrize("precision,n", [("fp32", 64), ("fp64", 96), ("fp32", 80), ("fp64", 128)])
+@pytest.mark.parametrize("x_tile,y_group", [(1, 0), (2, 0), (0, 1), (0, 2)])
+def test_tile_variants_match_oracle(precision, n, x_tile, y_group):
+    """Each tile variant the autotuner may pick, x tiles and y groups, against
+    the oracle over 3 sweeps."""
+    w = workloads.small_workload(n, 8, precision=precision, seed=97, rng_seed=98)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    smp.set_tuning("split", x_tile, y_group)
+    geo = smp.tuning()
+    smp.sweep(3)
+    s_gpu, p_gpu, _ = smp.state()
+    smp.close()
+    s_ref, p_ref = run_oracle(w, pb, 3)
+    err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+    print(f"n={n} {precision} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}) "
+          f"y_group={y_group} ({geo['y_units']} units): err_s={err_s:.3e} err_P={err_p:.3e}",
+          flush=True)
+    assert err_s < TOL[precision] and err_p < TOL[precision]
+
+
+def test_tuning_errors():
+    w = workloads.small_workload(32, 4, precision="fp32", seed=99, rng_seed=100)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    for bad in ((0, 3, 0), (0, 0, -1)):
+        with pytest.raises(binding.MFError) as e:
+            smp.set_tuning("split", bad[1], bad[2])
+        assert e.value.status == binding.MF_E_INVALID_ARG
+    assert smp.tuning()["x_tile"] == 0 and smp.tuning()["y_group"] == 0
+    smp.close()
 
 
 def test_switching_paths_mid_chain_matches_oracle():
@@ -80,6 +119,8 @@ def test_autotune_keeps_the_chain_and_picks_a_path():
     print("autotune", res, flush=True)
     assert res["path"] in ("split", "whole") and smp.x_path() == res["path"]
     assert all(np.isfinite(v) and v > 0 for v in res["ms"].values())
+    assert all(np.isfinite(v) and v > 0 for v in res["ms_x_tile"])
+    assert smp.tuning() == {k: v for k, v in res.items() if not k.startswith("ms")}
     s1, p1, n1 = smp.state()
     assert np.array_equal(s0, s1) and np.array_equal(p0, p1) and n0 == n1
     assert smp.recorded() == rec0
@@ -88,7 +129,7 @@ def test_autotune_keeps_the_chain_and_picks_a_path():
     # the default path and the last two on the chosen one
     ref2 = gpu_sampler(w, pb)
     ref2.sweep(3)
-    ref2.set_x_path(res["path"])
+    ref2.set_tuning(res["path"], res["x_tile"], res["y_group"])
     ref2.sweep(2)
     assert np.array_equal(smp.state()[0], ref2.state()[0])
 
