@@ -142,7 +142,7 @@ def bench_batched(args):
     for (n, _), smp in zip(workloads.BATCHED_SIZES, samplers):
         res = smp.autotune(trials=10)                         # before the graph is captured
         tuned[f"{n}^3"] = {k: res[k] for k in ("path", "x_tile", "y_group", "x_cols", "x_k1",
-                                                "y_units")}
+                                                "x_hist", "y_units")}
         tuned[f"{n}^3"]["ms"] = {"path": {k: _r5(v) for k, v in res["ms"].items()},
                                  "x_tile": [_r5(v) for v in res["ms_x_tile"]],
                                  "y_group": [_r5(v) for v in res["ms_y_group"]]}
@@ -682,7 +682,7 @@ def main():
                    "chains": 1,
                    "x_path": tune["path"],
                    "tuning": {k: tune[k] for k in ("x_tile", "y_group", "x_cols", "x_k1",
-                                                   "y_units")},
+                                                   "x_hist", "y_units")},
                    "autotune_ms_per_sweep": {k: _r5(v) for k, v in tune["ms"].items()},
                    "autotune_ms_x_tile": [_r5(v) for v in tune["ms_x_tile"]],
                    "autotune_ms_y_group": [_r5(v) for v in tune["ms_y_group"]],

@@ -222,20 +222,23 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
  * Path 1 (whole): the x-pass runs whole x pencils through LDS.  It is the
  * only path for N = 8, 16, 512.
  * On the split path two tile choices are open, three variants each:
- *  - x_tile: the x-pass workgroup's iy columns and k1 values (variant 0 is
- *    the library's rule; 1 and 2 are alternatives fixed per grid side, e.g.
- *    at 256: 128 x 2, 64 x 4, and 128 x 2 without the occupancy bound);
+ *  - x_tile: the x-pass workgroup (variant 0 is the library's tile rule,
+ *    e.g. 128 iy columns x 2 k1 values at 256, with 8 LDS shell histograms
+ *    per wave, for at most 255 bins; 1 is the same tile with 2 histograms
+ *    per wave, for any bin count; 2 is another tile shape fixed per grid
+ *    side, e.g. 64 x 4 at 256, with 2 histograms);
  *  - y_group: (kz, q) units per y-pass workgroup, the rule's G, G/2, G/4
  *    (at least 1).
  * Every choice gives the same chain up to rounding (the shell sums are
  * grouped by workgroup) and leaves the same state between sweeps, so choices
- * may change at any time.  The default is the split path with variants 0
- * where it exists.  Mixing sweeps and the Wiener filter always use the split
- * path with x-tile variant 0.
+ * may change at any time.  The default is the split path where it exists,
+ * x tile 0 (1 above 255 bins) and y group 0.  Mixing sweeps and the Wiener
+ * filter always use the split path with x tile 1.
  * mf_set_x_path: MF_E_UNSUPPORTED_SIZE for the split path outside 32..256.
  * mf_set_tuning / mf_get_tuning: the path and both variants at once;
  *   mf_get_tuning also fills the geometry they stand for.  MF_E_INVALID_ARG
- *   for a variant outside 0..2, MF_E_UNSUPPORTED_SIZE as mf_set_x_path.
+ *   for a variant outside 0..2 or an x tile whose histograms cannot hold the
+ *   problem's bins, MF_E_UNSUPPORTED_SIZE as mf_set_x_path.
  * mf_autotune: coordinate search over the split path's x tiles (y group 0),
  * then its y groups (with the best x tile), then that tuned split path
  * against the whole-pencil path.  Each stage times its candidates in turn,
@@ -257,6 +260,7 @@ typedef struct {
   int32_t x_cols;   /* out (mf_get_tuning): iy columns per x-pass workgroup */
   int32_t x_k1;     /* out: k1 values per split x-pass workgroup */
   int32_t y_units;  /* out: (kz, q) units per split y-pass workgroup */
+  int32_t x_hist;   /* out: LDS shell histograms per wave of the split x-pass */
 } mf_tuning;
 #define MF_TUNE_SLOTS 8
 mf_status mf_set_x_path(mf_problem* p, int32_t path);

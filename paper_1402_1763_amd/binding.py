@@ -60,6 +60,7 @@ class mf_tuning(ctypes.Structure):
         ("x_cols", ctypes.c_int32),
         ("x_k1", ctypes.c_int32),
         ("y_units", ctypes.c_int32),
+        ("x_hist", ctypes.c_int32),
     ]
 
 
@@ -448,7 +449,7 @@ class Sampler:
         t = mf_tuning()
         _check(load().mf_get_tuning(ctypes.c_void_p(self.handle), ctypes.byref(t)))
         return {"path": self.X_PATHS[t.x_path], "x_tile": t.x_tile, "y_group": t.y_group,
-                "x_cols": t.x_cols, "x_k1": t.x_k1, "y_units": t.y_units}
+                "x_cols": t.x_cols, "x_k1": t.x_k1, "y_units": t.y_units, "x_hist": t.x_hist}
 
     def set_tuning(self, path: str = "split", x_tile: int = 0, y_group: int = 0):
         t = mf_tuning(x_path=self.X_PATHS.index(path), x_tile=x_tile, y_group=y_group)

@@ -85,6 +85,16 @@ struct Geometry {
     if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::K1;
     else return 0;
   }
+  template <int V>
+  static constexpr int x_hist() {
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::HG;
+    else return 0;
+  }
+  template <int V>
+  static constexpr int x_max_bins() {
+    if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::MAX_BINS;
+    else return 0;
+  }
   static constexpr int xp_whole = N / mf::XTile<R, N>::P;
   static constexpr int ztiles = (N / mf::ZTile<R, N>::IXB) * (N / mf::ZTile<R, N>::P);
   static constexpr int zept = mf::ZTile<R, N>::EPT;
@@ -94,6 +104,8 @@ struct Shape {
   int xp_split[kTileVariants];   // split x-pass workgroups per kz plane, per tile variant
   int x_cols[kTileVariants];     // their iy columns and k1 values per workgroup
   int x_k1[kTileVariants];
+  int x_hist[kTileVariants];     // LDS histogram copies per wave
+  int x_max_bins[kTileVariants]; // most bins whose histograms fit the variant's LDS
   int y_units[kTileVariants];    // (kz, q) units per split y-pass workgroup, per variant
   int xp_whole;                  // whole-pencil x-pass workgroups per kz plane
   int ztiles;                    // z-pass tiles per chain
@@ -109,6 +121,9 @@ Shape shape_of(int n) {
     return Shape{{G::template split_wpp<0>(), G::template split_wpp<1>(), G::template split_wpp<2>()}, \
                  {G::template x_cols<0>(), G::template x_cols<1>(), G::template x_cols<2>()},   \
                  {G::template x_k1<0>(), G::template x_k1<1>(), G::template x_k1<2>()},         \
+                 {G::template x_hist<0>(), G::template x_hist<1>(), G::template x_hist<2>()},   \
+                 {G::template x_max_bins<0>(), G::template x_max_bins<1>(),                   \
+                  G::template x_max_bins<2>()},                                            \
                  {G::template y_units<0>(), G::template y_units<1>(), G::template y_units<2>()}, \
                  G::xp_whole, G::ztiles, G::zept};                                         \
   }
@@ -269,6 +284,8 @@ struct mf_problem {
   int graphs = 0;               // live graphs that captured this problem's sweep
   // x-pass workgroups of a path; the split path's with x-tile variant xv
   int n_wg(int path, int xv) const { return path == kPathSplit ? L.n_wg_split[xv] : L.n_wg_whole; }
+  // the default split x tile: 8 histogram copies per wave where they fit
+  int default_xvar() const { return desc.n_bins <= sh.x_max_bins[0] ? 0 : 1; }
   bool fp64() const { return desc.precision == MF_PREC_FP64; }
 };
 
@@ -342,18 +359,18 @@ void launch_xsplit(const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
   using XS = mf::XSTile<R, N, V>;
   const size_t tables = 2 * a.nb * sizeof(R) + (a.nb + 1) * 4;
   hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXSample, V>), dim3(XS::WPP, N / 2 + 1, nch),
-                     dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+                     dim3(XS::NT), mf::hist_doubles(XS::NHIST, a.nb, 1) * sizeof(double) + tables, st, a);
 }
 
 // xv, yv: split-path tile variants of the Gibbs x-pass and of the y-passes;
-// every other kernel runs variant 0.
+// the other x-pass modes (mixing, Wiener) run x-tile variant 1.
 template <typename R, int N>
 void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool whole, int xv,
               int yv) {
   using ZT = mf::ZTile<R, N>;
   using YT = mf::YTile<R, N>;
   using XT = mf::XTile<R, N>;
-  using XS = mf::XSTile<R, N>;
+  using XS = mf::XSTile<R, N, 1>;   // the modes other than Gibbs sampling
   constexpr bool can_split = mf::split_x<N>();
   const bool split = can_split && !whole;
   const dim3 zgrid(N / ZT::P, N / ZT::IXB, nch), zgrid1(N / ZT::P, N / ZT::IXB, 1);
@@ -400,13 +417,13 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
       break;
     case kXDetK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet>), dim3(XS::WPP, N / 2 + 1, nch),
-                           dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXDet, 1>), dim3(XS::WPP, N / 2 + 1, nch),
+                           dim3(XS::NT), mf::hist_doubles(XS::NHIST, a.nb, 1) * sizeof(double) + tables, st, a);
       break;
     case kXMixK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXMix>), dim3(XS::WPP, N / 2 + 1, nch),
-                           dim3(XS::NT), 2 * XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXMix, 1>), dim3(XS::WPP, N / 2 + 1, nch),
+                           dim3(XS::NT), mf::hist_doubles(XS::NHIST, a.nb, 2) * sizeof(double) + tables, st, a);
       break;
     case kXMixInvK:
       if constexpr (can_split)
@@ -418,8 +435,8 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
       break;
     case kXAdjK:
       if constexpr (can_split)
-        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXAdj>), dim3(XS::WPP, N / 2 + 1, nch),
-                           dim3(XS::NT), XS::NHIST * a.nb * sizeof(double) + tables, st, a);
+        hipLaunchKernelGGL((mf::xsplit_kernel<R, N, mf::kXAdj, 1>), dim3(XS::WPP, N / 2 + 1, nch),
+                           dim3(XS::NT), mf::hist_doubles(XS::NHIST, a.nb, 1) * sizeof(double) + tables, st, a);
       break;
     case kX:
       if constexpr (can_split) {
@@ -431,7 +448,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
         }
       }
       hipLaunchKernelGGL((mf::xpass_kernel<R, N>), dim3(N / XT::P, N / 2 + 1, nch), dim3(XT::NT),
-                         XT::NHIST * a.nb * sizeof(double) + tables, st, a);
+                         mf::hist_doubles(XT::NHIST, a.nb, 1) * sizeof(double) + tables, st, a);
       break;
     case kTable:
       hipLaunchKernelGGL((mf::pk_table_kernel<R>), dim3((a.nb + 63) / 64, nch), dim3(64), 0, st, a);
@@ -457,11 +474,11 @@ void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st, b
 }
 
 // path < 0: the problem's Gibbs-sweep path and tile variants; a given path
-// (the mixing sweep's split path) runs tile variant 0 of the x-pass.
+// (the mixing sweep's split path) runs x-tile variant 1.
 mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t st, int path = -1,
                          int pk_mode = mf::kPkDraw) {
   const int nch = p->desc.n_chains;
-  const int xv = path < 0 ? p->xvar : 0, yv = p->yvar;
+  const int xv = path < 0 ? p->xvar : 1, yv = p->yvar;
   if (path < 0) path = p->xpath;
   if (p->fp64()) {
     auto a = args_of<double>(p, path, xv);
@@ -720,6 +737,7 @@ mf_status mf_init_problem(const mf_chain_desc* desc, const double* const* data,
   p->tau = tau;
   p->sweep = 0;
   p->xpath = (n >= 32 && n <= 256) ? kPathSplit : kPathWhole;
+  p->xvar = p->default_xvar();
   hipStream_t hs = static_cast<hipStream_t>(stream);
 
   auto cleanup = [&](mf_status r) {
@@ -1027,6 +1045,10 @@ mf_status mf_set_tuning(mf_problem* p, const mf_tuning* t) {
   if (!p || !t) return fail(MF_E_INVALID_ARG, "NULL argument");
   if (t->x_tile < 0 || t->x_tile >= kTileVariants || t->y_group < 0 || t->y_group >= kTileVariants)
     return fail(MF_E_INVALID_ARG, "tile variants must be 0..%d", kTileVariants - 1);
+  if (t->x_path == kPathSplit && p->desc.n >= 32 && p->desc.n <= 256 &&
+      p->desc.n_bins > p->sh.x_max_bins[t->x_tile])
+    return fail(MF_E_INVALID_ARG, "x tile %d holds histograms for at most %d bins (problem has %d)",
+                t->x_tile, p->sh.x_max_bins[t->x_tile], p->desc.n_bins);
   const mf_status st = mf_set_x_path(p, t->x_path);
   if (st != MF_OK) return st;
   p->xvar = t->x_tile;
@@ -1042,6 +1064,7 @@ mf_status mf_get_tuning(const mf_problem* p, mf_tuning* t) {
   const bool split = p->xpath == kPathSplit;
   t->x_cols = split ? p->sh.x_cols[p->xvar] : 0;
   t->x_k1 = split ? p->sh.x_k1[p->xvar] : 0;
+  t->x_hist = split ? p->sh.x_hist[p->xvar] : 0;
   t->y_units = split ? p->sh.y_units[p->yvar] : 0;
   return MF_OK;
 }
@@ -1088,7 +1111,8 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
   const bool can_split = p->desc.n >= 32 && p->desc.n <= 256;
   if (!can_split) {
     p->xpath = kPathWhole;
-    p->xvar = p->yvar = 0;
+    p->xvar = p->default_xvar();
+    p->yvar = 0;
     return picked ? mf_get_tuning(p, picked) : MF_OK;
   }
   // every candidate's sweeps must fit below the 2^32 sweep-index bound; the
@@ -1130,11 +1154,13 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
     return best;
   };
   p->xpath = kPathSplit;
-  p->xvar = p->yvar = 0;
+  p->xvar = p->default_xvar();
+  p->yvar = 0;
   st = mf_gibbs_sweep(p, warm, stream);   // device warm-up
   // 1. x tiles on the split path, y group 0
   std::vector<Cand> xs;
-  for (int v = 0; v < kTileVariants; ++v) xs.push_back({kPathSplit, v, 0, 2 + v});
+  for (int v = 0; v < kTileVariants; ++v)
+    if (p->desc.n_bins <= p->sh.x_max_bins[v]) xs.push_back({kPathSplit, v, 0, 2 + v});
   run_stage(xs);
   const int best_x = st == MF_OK ? xs[pick(xs)].xv : 0;
   // 2. y groups with the best x tile (groups of equal size are timed once)
@@ -1159,7 +1185,7 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
   }
   if (st != MF_OK) return st;
   p->xpath = whole ? kPathWhole : kPathSplit;
-  p->xvar = whole ? 0 : best_x;
+  p->xvar = whole ? p->default_xvar() : best_x;
   p->yvar = whole ? 0 : best_y;
   return picked ? mf_get_tuning(p, picked) : MF_OK;
 }
@@ -1404,7 +1430,7 @@ void with_n(int n, F&& f) {
 template <typename R>
 mf::SweepArgs<R> wiener_args(const mf_problem* p, int c0, const R* coef, R* table, double* pkg,
                              double* gacc) {
-  mf::SweepArgs<R> a = args_of<R>(p, kPathSplit, 0);
+  mf::SweepArgs<R> a = args_of<R>(p, kPathSplit, 1);
   a.coef = coef;
   a.table = table;
   a.pk = pkg;

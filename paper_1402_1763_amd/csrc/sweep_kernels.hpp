@@ -957,24 +957,38 @@ __device__ __forceinline__ void filter_slot(cx<R>* v, int q, int iy, int kz, con
   }
 }
 
+// Doubles between consecutive LDS histogram copies: nb rounded up to an odd
+// number, so that the copies of one bin fall on different LDS banks (lanes
+// of one wave that add to the same bin of different copies then do not
+// collide on a bank).
+__host__ __device__ constexpr int hist_stride(int nb) { return nb | 1; }
+
+// Doubles of LDS that the NH histogram sets of a workgroup take (NHIST
+// copies each).
+__host__ __device__ constexpr int hist_doubles(int nhist, int nb, int nh) {
+  return nh * nhist * hist_stride(nb);
+}
+
 // Shared prologue / epilogue of the x-pass kernels: LDS tables and per-wave
-// histograms (HG copies per wave by lane), then one partial per workgroup.
-// NH histogram sets (1, or 2 for the mixing sweep) of NHIST copies each.
+// histograms (HG copies per wave by lane: lane l adds to copy l mod HG), then
+// one partial per workgroup.  NH histogram sets (1, or 2 for the mixing
+// sweep) of NHIST copies each, copies hist_stride(nb) doubles apart.
 template <typename R, int NT, int NHIST, int HG, int NH = 1>
 __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c, double* dyn,
                                                     int n) {
-  const int nb = a.nb, tid = threadIdx.x;
+  const int nb = a.nb, tid = threadIdx.x, hs = hist_stride(nb);
+  constexpr int hg = HG, nhist = NHIST;
   double* hist = dyn;
-  R* tab = reinterpret_cast<R*>(hist + NH * NHIST * nb);
+  R* tab = reinterpret_cast<R*>(hist + NH * nhist * hs);
   int32_t* qthr = reinterpret_cast<int32_t*>(tab + 2 * nb);
-  for (int i = tid; i < NH * NHIST * nb; i += NT) hist[i] = 0.0;
+  for (int i = tid; i < NH * nhist * hs; i += NT) hist[i] = 0.0;
   for (int i = tid; i < 2 * nb; i += NT) tab[i] = a.table[static_cast<size_t>(c) * 2 * nb + i];
   for (int i = tid; i <= nb; i += NT) qthr[i] = i < nb ? a.qthr[i] : INT32_MAX;
   DrawCtx<R> d;
   d.qthr = qthr;
   d.tab = reinterpret_cast<const cx<R>*>(tab);
-  d.hist = hist + ((tid / 64) * HG + (tid % HG)) * nb;
-  d.hist2 = NH == 2 ? d.hist + NHIST * nb : nullptr;
+  d.hist = hist + ((tid / 64) * hg + (tid % hg)) * hs;
+  d.hist2 = NH == 2 ? d.hist + nhist * hs : nullptr;
   d.qscale = static_cast<float>(4.0 * nb * nb / (3.0 * n * n));
   d.nb = nb;
   d.chain = a.chain0 + c;
@@ -985,23 +999,25 @@ __device__ __forceinline__ DrawCtx<R> draw_prologue(const SweepArgs<R>& a, int c
 // The workgroup's plane kz sets the weight w of its modes in the full-grid
 // sums: 1 on kz = 0 and kz = N/2, 2 elsewhere (each mode stands for itself
 // and its conjugate).
+// `hist` is the set's first copy (NHIST copies).
 template <typename R, int NT, int NHIST>
 __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, double* hist, int wg,
                                               double wgt, double* partials = nullptr) {
   __syncthreads();   // all histogram atomics are done
-  const int nb = a.nb, tid = threadIdx.x;
+  const int nb = a.nb, tid = threadIdx.x, hs = hist_stride(nb);
   double* part = (partials ? partials : a.partials) + static_cast<size_t>(c) * a.n_wg_x * nb + wg;
   // Fixed-order reduction of the NHIST copies: G groups of PER consecutive
   // copies, each summed in ascending order into its first copy (every entry is
   // read and written by one thread only), then the G group sums in order.
-  constexpr int G = NHIST >= 16 ? 8 : 1;
+  // G = gcd(NHIST, 8) from 16 copies up, else 1.
+  constexpr int G = NHIST < 16 ? 1 : (NHIST % 8 == 0 ? 8 : (NHIST % 4 == 0 ? 4 : (NHIST % 2 == 0 ? 2 : 1)));
   constexpr int PER = NHIST / G;
   if (G > 1) {
     for (int it = tid; it < nb * G; it += NT) {
       const int b = it % nb, g = it / nb;
       double s = 0.0;
-      for (int w = 0; w < PER; ++w) s += hist[(g * PER + w) * nb + b];
-      hist[g * PER * nb + b] = s;
+      for (int w = 0; w < PER; ++w) s += hist[(g * PER + w) * hs + b];
+      hist[g * PER * hs + b] = s;
     }
     __syncthreads();
   }
@@ -1010,7 +1026,7 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
   constexpr int COUNT = G > 1 ? G : NHIST;
   for (int b = tid; b < nb; b += NT) {
     double s = 0.0;
-    for (int g = 0; g < COUNT; ++g) s += hist[g * STEP * nb + b];
+    for (int g = 0; g < COUNT; ++g) s += hist[g * STEP * hs + b];
     part[static_cast<size_t>(b) * a.n_wg_x] = wgt * s;
   }
 }
@@ -1023,21 +1039,25 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
 // HBM rewards: sides divisible by 64 with NA >= 4 take P = min(N, 128) (1 KiB
 // runs in FP32) and K1 = 256 / P, so NA / K1 workgroups share a column block.
 // At 256^3 that took the pass from 41.7 us (P = 16) to 36.7 us.  The other
-// sides take every k1 of a column.  Variants 1 and 2 are the alternative
-// tiles the autotuner tries (xs_alt); variant 0 is this rule.
-//   (P, K1) of variants 1, 2 per side: 256: (64, 4), (128, 2) without the
-//   5-wave bound; 128: (64, 4), (32, 8); 96: (96, 2), (48, 6);
-//   80: (80, 1), (16, 5); 64: (64, 2), (32, 4); 48: (48, 1), (16, 3);
-//   32: (32, 1), (16, 2).
-__host__ __device__ constexpr int xs_alt(int n, int v, bool k1) {
+// sides take every k1 of a column.
+// Variants: 0 is this tile with 8 LDS histogram copies per wave, for up to
+// 255 bins (neighbouring lanes hold neighbouring iy, whose bins are mostly
+// equal, so more copies mean fewer lanes adding to one address per
+// instruction: the 256^3 x-pass takes 32.0 us against 33.6 us with 2
+// copies); 1 is the same tile with 2 copies, for any bin count and for the
+// mixing sweep and the Wiener iteration; 2 is another tile shape (xs_alt)
+// with 2 copies.  The autotuner chooses among them.
+//   (P, K1) of variant 2 per side: 256: (64, 4); 128: (64, 4); 96: (96, 2);
+//   80: (80, 1); 64: (64, 2); 48: (48, 1); 32: (32, 1).
+__host__ __device__ constexpr int xs_alt(int n, bool k1) {
   switch (n) {
-    case 256: return v == 1 ? (k1 ? 4 : 64) : (k1 ? 2 : 128);
-    case 128: return v == 1 ? (k1 ? 4 : 64) : (k1 ? 8 : 32);
-    case 96: return v == 1 ? (k1 ? 2 : 96) : (k1 ? 6 : 48);
-    case 80: return v == 1 ? (k1 ? 1 : 80) : (k1 ? 5 : 16);
-    case 64: return v == 1 ? (k1 ? 2 : 64) : (k1 ? 4 : 32);
-    case 48: return v == 1 ? (k1 ? 1 : 48) : (k1 ? 3 : 16);
-    default: return v == 1 ? (k1 ? 1 : n) : (k1 ? 2 : 16);
+    case 256: return k1 ? 4 : 64;
+    case 128: return k1 ? 4 : 64;
+    case 96: return k1 ? 2 : 96;
+    case 80: return k1 ? 1 : 80;
+    case 64: return k1 ? 2 : 64;
+    case 48: return k1 ? 1 : 48;
+    default: return k1 ? 1 : n;
   }
 }
 
@@ -1046,17 +1066,19 @@ struct XSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
   static constexpr bool WIDE = N % 64 == 0 && NA >= 4 && NA % 4 == 0;
   static constexpr int P0 = WIDE ? (N < 128 ? N : 128) : divisor_below(N, 256 / NA);
-  static constexpr int P = V == 0 ? P0 : xs_alt(N, V, false);          // columns per workgroup
-  static constexpr int K1 = V == 0 ? (WIDE ? 256 / P0 : NA) : xs_alt(N, V, true);   // k1 values
+  static constexpr int P = V < 2 ? P0 : xs_alt(N, false);          // columns per workgroup
+  static constexpr int K1 = V < 2 ? (WIDE ? 256 / P0 : NA) : xs_alt(N, true);   // k1 values
   static constexpr int KB = NA / K1;                 // workgroups per column block
   static constexpr int NT = P * K1;
   static constexpr int WPP = (N / P) * KB;           // workgroups per kz plane
-  static constexpr int HG = 2;
-  static constexpr int NHIST = ((NT + 63) / 64) * HG;
+  static constexpr int NWAVES = (NT + 63) / 64;
+  static constexpr int HG = V == 0 ? 8 : 2;          // LDS histogram copies per wave
+  static constexpr int NHIST = NWAVES * HG;
+  static constexpr int MAX_BINS = V == 0 ? 255 : 1024;   // 8 copies: 64 KiB of LDS at most
   static_assert(N % P == 0 && NA % K1 == 0 && NT <= 1024, "x-pass tile must cover the plane");
   // FP32 at N = 256 would take 98 VGPRs (4 waves per SIMD); held to 96 (5
   // waves, no spill) the pass runs 33.2 us instead of 35.5 us.
-  static constexpr int MIN_WAVES = (V == 0 && sizeof(R) == 4 && N == 256) ? 5 : 1;
+  static constexpr int MIN_WAVES = (V < 2 && sizeof(R) == 4 && N == 256) ? 5 : 1;
 };
 
 template <typename R, int N, int XM, int V = 0>
@@ -1064,7 +1086,7 @@ __global__ void __launch_bounds__((XSTile<R, N, V>::NT), (XSTile<R, N, V>::MIN_W
 xsplit_kernel(SweepArgs<R> a) {
   using T = XSTile<R, N, V>;
   constexpr int P = T::P, NT = T::NT, NA = T::NA;
-  extern __shared__ double dyn[];      // hist[NHIST][nb], table (2 nb R), qthr (nb + 1)
+  extern __shared__ double dyn[];      // histograms (hist_doubles), table (2 nb R), qthr (nb + 1)
   const int tid = threadIdx.x;
   const int iy0 = (blockIdx.x / T::KB) * P;
   const int kz = blockIdx.y;
@@ -1093,7 +1115,8 @@ xsplit_kernel(SweepArgs<R> a) {
   const int wg = blockIdx.y * gridDim.x + blockIdx.x;
   const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
   if (XM != kXDet) draw_epilogue<R, NT, T::NHIST>(a, c, dyn, wg, wgt);
-  if (XM == kXMix) draw_epilogue<R, NT, T::NHIST>(a, c, dyn + T::NHIST * a.nb, wg, wgt, a.partials2);
+  if (XM == kXMix)
+    draw_epilogue<R, NT, T::NHIST>(a, c, dyn + T::NHIST * hist_stride(a.nb), wg, wgt, a.partials2);
 }
 
 // Second half of the mixing sweep's x-pass: every mode of bin b, stored by
@@ -1101,9 +1124,9 @@ xsplit_kernel(SweepArgs<R> a) {
 // sqrt(S^'_b / S^_b) from the Metropolis-Hastings move, then the inverse
 // 16-point DFT restores the split layout for the inverse y-pass.
 template <typename R, int N>
-__global__ void __launch_bounds__((XSTile<R, N>::NT))
+__global__ void __launch_bounds__((XSTile<R, N, 1>::NT))
 xmixinv_kernel(SweepArgs<R> a) {
-  using T = XSTile<R, N>;
+  using T = XSTile<R, N, 1>;
   constexpr int P = T::P, NT = T::NT, NA = T::NA;
   extern __shared__ double dyn[];      // ratio (nb R), qthr (nb + 1)
   const int tid = threadIdx.x, nb = a.nb;

@@ -1,7 +1,9 @@
 """GPU edge cases: zero sweeps, and the largest bin count (1024 bins, most of
-them empty at small |k|) on the 256^3 grid, where the per-wave FP64 shell
-histograms need the most LDS: about 78 KB per x-pass workgroup for an FP32
-Gibbs sweep and 152 KB for an FP64 mixing sweep."""
+them empty at small |k|) on the 256^3 grid, where the FP64 shell histograms
+need the most LDS (one copy per wave instead of 8, 33 KB per x-pass
+workgroup for an FP32 Gibbs sweep and 66 KB for an FP64 mixing sweep);
+the sweep-index bound; mixing sweeps with P held fixed; diagnostics under a
+live graph."""
 import numpy as np
 import pytest
 

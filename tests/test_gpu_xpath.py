@@ -52,7 +52,8 @@ def test_every_path_and_tile_at_256_matches_oracle():
         geo = smp.tuning()
         smp.close()
         err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
-        print(f"  {path} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}): err_s={err_s:.3e} "
+        print(f"  {path} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}, {geo['x_hist']} "
+              f"histograms per wave): err_s={err_s:.3e} "
               f"err_P={err_p:.3e}", flush=True)
         assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
 
@@ -72,7 +73,8 @@ def test_tile_variants_match_oracle(precision, n, x_tile, y_group):
     smp.close()
     s_ref, p_ref = run_oracle(w, pb, 3)
     err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
-    print(f"n={n} {precision} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}) "
+    print(f"n={n} {precision} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}, "
+          f"{geo['x_hist']} histograms) "
           f"y_group={y_group} ({geo['y_units']} units): err_s={err_s:.3e} err_P={err_p:.3e}",
           flush=True)
     assert err_s < TOL[precision] and err_p < TOL[precision]
@@ -86,7 +88,18 @@ def test_tuning_errors():
         with pytest.raises(binding.MFError) as e:
             smp.set_tuning("split", bad[1], bad[2])
         assert e.value.status == binding.MF_E_INVALID_ARG
-    assert smp.tuning()["x_tile"] == 0 and smp.tuning()["y_group"] == 0
+    assert smp.tuning()["x_tile"] == 0 and smp.tuning()["y_group"] == 0   # the defaults
+    smp.close()
+    # 8 histograms per wave (x tile 0) hold at most 255 bins
+    w = workloads.small_workload(32, 300, precision="fp32", seed=99, rng_seed=100)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    assert smp.tuning()["x_tile"] == 1          # the default above 255 bins
+    with pytest.raises(binding.MFError) as e:
+        smp.set_tuning("split", 0, 0)
+    assert e.value.status == binding.MF_E_INVALID_ARG
+    res = smp.autotune(trials=1)
+    assert np.isnan(res["ms_x_tile"][0]) and res["x_tile"] != 0
     smp.close()
 
 
