@@ -135,8 +135,8 @@ Shape shape_of(int n) {
 }
 
 struct Layout {
-  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, tobs, coef, spec, staging,
-      rinv, total;
+  size_t ctr, tw, qthr, counts, tau, pk, table, status, partials, ratio, tobs, coef, omw, spec,
+      staging, rinv, total;
   size_t spec_elems, spec_stride;
   int n_wg_split[kTileVariants];   // split x-pass workgroups (one shell partial each) per variant
   int n_wg_whole;                  // whole-pencil x-pass workgroups
@@ -175,6 +175,7 @@ Layout make_layout(const mf_chain_desc& d) {
   L.ratio = take(nc * nb * 8);
   L.tobs = take(nc * static_cast<size_t>(sh.ztiles) * 4);
   L.coef = take(nc * 2 * m * rs);
+  L.omw = take(nc * m * rs);      // tau R^2 / N = 1 - alpha per voxel (Wiener filter only)
   L.spec = take(nc * L.spec_stride * 2 * rs);
   L.staging = take(m * rs);
   L.rinv = take(d.has_response ? nc * m * 8 : 0);   // 1 / R per voxel (0 unobserved), FP64
@@ -568,12 +569,16 @@ bool observed(const double* noise_var, const double* response, size_t i) {
 // beta = tau R d / N; (1, 0) where unobserved.  alpha is 0 in exact
 // arithmetic where N / R^2 is smallest (tau is that minimum); rounding of
 // tau R^2 / N there can leave -1 ulp, which is set back to 0.
+// Also o = tau R^2 / N (0 where unobserved) per voxel, entry order
+// [entry][2], for the Wiener filter's data-dependent coefficients.
 template <typename R, int N>
-void permute_coef(std::vector<R>& out, std::vector<uint32_t>& obs, const double* data,
-                  const double* noise_var, const double* response, double tau) {
+void permute_coef(std::vector<R>& out, std::vector<R>& omw, std::vector<uint32_t>& obs,
+                  const double* data, const double* noise_var, const double* response,
+                  double tau) {
   using T = mf::ZTile<R, N>;
   const int tiles = (N / T::IXB) * (N / T::P);
   out.assign(static_cast<size_t>(2) * N * N * N, R(0));
+  omw.assign(static_cast<size_t>(N) * N * N, R(0));
   obs.assign(tiles, 0);
   auto resp = [&](size_t i) { return response ? response[i] : 1.0; };
   auto alpha = [&](size_t i) {
@@ -583,17 +588,24 @@ void permute_coef(std::vector<R>& out, std::vector<uint32_t>& obs, const double*
   auto beta = [&](size_t i) {
     return observed(noise_var, response, i) ? tau * resp(i) * data[i] / noise_var[i] : 0.0;
   };
+  auto one_minus_alpha = [&](size_t i) {
+    return observed(noise_var, response, i)
+               ? std::min(1.0, tau * resp(i) * resp(i) / noise_var[i]) : 0.0;
+  };
   for (int tile = 0; tile < tiles; ++tile)
     for (int e = 0; e < T::EPT; ++e)
       for (int tid = 0; tid < T::NT; ++tid) {
         int ix = 0, iya = 0, n = 0;
         mf::zpass_coef_voxel<R, N>(tile, e, tid, ix, iya, n);
         const size_t va = (static_cast<size_t>(ix) * N + iya) * N + n, vb = va + N;
-        R* o = &out[((static_cast<size_t>(tile) * T::EPT + e) * T::NT + tid) * 4];
+        const size_t entry = (static_cast<size_t>(tile) * T::EPT + e) * T::NT + tid;
+        R* o = &out[entry * 4];
         o[0] = static_cast<R>(alpha(va));
         o[1] = static_cast<R>(alpha(vb));
         o[2] = static_cast<R>(beta(va));
         o[3] = static_cast<R>(beta(vb));
+        omw[entry * 2] = static_cast<R>(one_minus_alpha(va));
+        omw[entry * 2 + 1] = static_cast<R>(one_minus_alpha(vb));
         if (observed(noise_var, response, va) || observed(noise_var, response, vb))
           obs[tile] |= 1u << e;
       }
@@ -602,17 +614,19 @@ void permute_coef(std::vector<R>& out, std::vector<uint32_t>& obs, const double*
 template <typename R>
 mf_status upload_coef(mf_problem* p, int c, const double* data, const double* noise_var,
                       const double* response, double tau, hipStream_t st) {
-  std::vector<R> buf;
+  std::vector<R> buf, omw;
   std::vector<uint32_t> obs;
   switch (p->desc.n) {
 #define MF_PERMUTE(NN) \
-  case NN: permute_coef<R, NN>(buf, obs, data, noise_var, response, tau); break;
+  case NN: permute_coef<R, NN>(buf, omw, obs, data, noise_var, response, tau); break;
     MF_PERMUTE(8) MF_PERMUTE(16) MF_PERMUTE(32) MF_PERMUTE(48) MF_PERMUTE(64) MF_PERMUTE(80)
     MF_PERMUTE(96) MF_PERMUTE(128) MF_PERMUTE(256) MF_PERMUTE(512)
 #undef MF_PERMUTE
   }
   MF_HIP(hipMemcpyAsync(p->ws + p->L.coef + static_cast<size_t>(c) * buf.size() * sizeof(R),
                         buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st));
+  MF_HIP(hipMemcpyAsync(p->ws + p->L.omw + static_cast<size_t>(c) * omw.size() * sizeof(R),
+                        omw.data(), omw.size() * sizeof(R), hipMemcpyHostToDevice, st));
   MF_HIP(hipMemcpyAsync(p->ws + p->L.tobs + static_cast<size_t>(c) * obs.size() * 4, obs.data(),
                         obs.size() * 4, hipMemcpyHostToDevice, st));
   if (p->obs_chunks.size() < static_cast<size_t>(p->desc.n_chains)) p->obs_chunks.resize(p->desc.n_chains);
@@ -1425,6 +1439,13 @@ void with_n(int n, F&& f) {
   }
 }
 
+// o = tau R^2 / N of problem chain c, z-pass entry order.
+template <typename R>
+const R* omw_of(const mf_problem* p, int c) {
+  const size_t m = static_cast<size_t>(p->desc.n) * p->desc.n * p->desc.n;
+  return reinterpret_cast<const R*>(p->ws + p->L.omw) + static_cast<size_t>(c) * m;
+}
+
 // Sweep arguments of the deterministic iteration of chains c0 .. c0 + nc - 1
 // (grid z = nc; chain c of the launch is problem chain c0 + c).
 template <typename R>
@@ -1512,7 +1533,7 @@ mf_status wiener_forward(mf_problem* p, int c0, const double* d, const double* p
     with_n(n, [&](auto nn) {
       constexpr int N = decltype(nn)::value;
       hipLaunchKernelGGL((mf::wiener_coef_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
-                         st, coef, wcoef, d + c * m, entries);
+                         st, coef, omw_of<R>(p, c0 + c), wcoef, d + c * m, entries);
     });
     hipLaunchKernelGGL((mf::wiener_table_kernel<R>), dim3((nb + 63) / 64), dim3(64), 0, st,
                        pk + c * nb, reinterpret_cast<double*>(g + W.pkg) + c * nb,
@@ -1540,7 +1561,7 @@ mf_status wiener_forward(mf_problem* p, int c0, const double* d, const double* p
     with_n(n, [&](auto nn) {
       constexpr int N = decltype(nn)::value;
       hipLaunchKernelGGL((mf::wiener_chi2_kernel<R, N>), dim3(W.nblk), dim3(mf::kWienerThreads), 0,
-                         st, reinterpret_cast<const R*>(g + W.wcoef) + c * 2 * m, d + c * m, s,
+                         st, omw_of<R>(p, c0 + c), d + c * m, s,
                          p->tau[c0 + c], reinterpret_cast<double*>(g + W.partial) + c * W.nblk,
                          s_out ? s_out + c * m : nullptr, entries);
     });
@@ -1592,8 +1613,7 @@ mf_status wiener_backward(mf_problem* p, int c0, const double* d, char* g, const
         with_n(n, [&](auto nn) {
           constexpr int N = decltype(nn)::value;
           hipLaunchKernelGGL((mf::wiener_grad_direct_kernel<R, N>), dim3(W.nblk),
-                             dim3(mf::kWienerThreads), 0, st,
-                             reinterpret_cast<const R*>(g + W.wcoef) + c * 2 * m, d + c * m, s,
+                             dim3(mf::kWienerThreads), 0, st, omw_of<R>(p, c0 + c), d + c * m, s,
                              p->tau[c0 + c], grad_d + c * m, entries);
         });
       }
@@ -1619,8 +1639,7 @@ mf_status wiener_backward(mf_problem* p, int c0, const double* d, char* g, const
     with_n(n, [&](auto nn) {
       constexpr int N = decltype(nn)::value;
       hipLaunchKernelGGL((mf::wiener_grad_adjoint_kernel<R, N>), dim3(W.nblk),
-                         dim3(mf::kWienerThreads), 0, st,
-                         reinterpret_cast<const R*>(g + W.wcoef) + c * 2 * m, acc + c * m,
+                         dim3(mf::kWienerThreads), 0, st, omw_of<R>(p, c0 + c), acc + c * m,
                          grad_d + c * m, entries);
     });
     hipLaunchKernelGGL(mf::wiener_grad_pk_kernel, dim3((nb + 63) / 64), dim3(64), 0, st,
@@ -1756,7 +1775,8 @@ mf_status logdet_run(mf_problem* p, int c0, const double* pk, int n_iter, int n_
       with_n(n, [&](auto nn) {
         constexpr int N = decltype(nn)::value;
         hipLaunchKernelGGL((mf::probe_coef_kernel<R, N>), dim3(nblk), dim3(mf::kWienerThreads), 0,
-                           st, coef, wcoef + static_cast<size_t>(c) * 2 * m, p->tau[c0 + c],
+                           st, coef, omw_of<R>(p, c0 + c), wcoef + static_cast<size_t>(c) * 2 * m,
+                           p->tau[c0 + c],
                            probe0 + static_cast<uint32_t>(j), p->desc.chain_id + c0 + c, a.key0,
                            a.key1, entries);
       });

@@ -36,21 +36,23 @@ __device__ __forceinline__ void entry_voxels(size_t idx, size_t& va, size_t& vb)
   vb = va + N;
 }
 
-// wcoef = (alpha_a, alpha_b, (1 - alpha_a) d_a, (1 - alpha_b) d_b): the
-// messenger coefficients of the problem's noise model with new data d (FP64,
-// [ix][iy][iz]); beta = tau d / N = (1 - alpha) d.
+// wcoef = (alpha_a, alpha_b, o_a d_a, o_b d_b): the messenger coefficients
+// of the problem's noise model with new data d (FP64, [ix][iy][iz]); beta =
+// tau d / N = o d with o = tau / N = 1 - alpha (with R = 1, after the
+// rescaling by R).  o comes from the problem's own array (formed in FP64 and
+// rounded once), not from 1 - alpha: in FP32, 1 - alpha would lose the
+// relative precision 6e-8 N / tau where tau << N.
 template <typename R, int N>
 __global__ void __launch_bounds__(kWienerThreads)
-wiener_coef_kernel(const R* coef, R* wcoef, const double* d, size_t entries) {
+wiener_coef_kernel(const R* coef, const R* omw, R* wcoef, const double* d, size_t entries) {
   const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
   if (idx >= entries) return;
   size_t va = 0, vb = 0;
   entry_voxels<R, N>(idx, va, vb);
-  const R aa = coef[idx * 4], ab = coef[idx * 4 + 1];
-  wcoef[idx * 4] = aa;
-  wcoef[idx * 4 + 1] = ab;
-  wcoef[idx * 4 + 2] = static_cast<R>((1.0 - static_cast<double>(aa)) * d[va]);
-  wcoef[idx * 4 + 3] = static_cast<R>((1.0 - static_cast<double>(ab)) * d[vb]);
+  wcoef[idx * 4] = coef[idx * 4];
+  wcoef[idx * 4 + 1] = coef[idx * 4 + 1];
+  wcoef[idx * 4 + 2] = static_cast<R>(static_cast<double>(omw[idx * 2]) * d[va]);
+  wcoef[idx * 4 + 3] = static_cast<R>(static_cast<double>(omw[idx * 2 + 1]) * d[vb]);
 }
 
 // Grid-unit P (P / V_cell) and the filter table (A_b = f_b / M, B_b unused).
@@ -77,13 +79,13 @@ __global__ void scale_kernel(const double* x, const double* w, double* y, size_t
 
 // Probe coefficients of the log-determinant estimator: (alpha, beta_z) with
 // beta_z = tau R z / N for the probe z = sgn(R) sqrt(N) xi, i.e.
-// beta_z = sqrt(tau (1 - alpha)) xi, since 1 - alpha = tau R^2 / N.  xi = +-1
+// beta_z = sqrt(tau o) xi with o = tau R^2 / N = 1 - alpha.  xi = +-1
 // of voxel v comes from Philox counter (v div 4, probe, kPhaseProbe, chain),
 // word v mod 4, top bit set -> -1.
 template <typename R, int N>
 __global__ void __launch_bounds__(kWienerThreads)
-probe_coef_kernel(const R* coef, R* wcoef, double tau, uint32_t probe, uint32_t chain,
-                  uint32_t k0, uint32_t k1, size_t entries) {
+probe_coef_kernel(const R* coef, const R* omw, R* wcoef, double tau, uint32_t probe,
+                  uint32_t chain, uint32_t k0, uint32_t k1, size_t entries) {
   const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
   if (idx >= entries) return;
   size_t va = 0, vb = 0;
@@ -93,11 +95,10 @@ probe_coef_kernel(const R* coef, R* wcoef, double tau, uint32_t probe, uint32_t 
     const uint32_t x = (v & 3) == 0 ? w.x0 : (v & 3) == 1 ? w.x1 : (v & 3) == 2 ? w.x2 : w.x3;
     return (x >> 31) ? -1.0 : 1.0;
   };
-  const R aa = coef[idx * 4], ab = coef[idx * 4 + 1];
-  wcoef[idx * 4] = aa;
-  wcoef[idx * 4 + 1] = ab;
-  wcoef[idx * 4 + 2] = static_cast<R>(sqrt(tau * (1.0 - static_cast<double>(aa))) * sign(va));
-  wcoef[idx * 4 + 3] = static_cast<R>(sqrt(tau * (1.0 - static_cast<double>(ab))) * sign(vb));
+  wcoef[idx * 4] = coef[idx * 4];
+  wcoef[idx * 4 + 1] = coef[idx * 4 + 1];
+  wcoef[idx * 4 + 2] = static_cast<R>(sqrt(tau * static_cast<double>(omw[idx * 2])) * sign(va));
+  wcoef[idx * 4 + 3] = static_cast<R>(sqrt(tau * static_cast<double>(omw[idx * 2 + 1])) * sign(vb));
 }
 
 // out_b += scale (G1_b - f_b G0_b) / (tau^2 V_cell), f_b = P_b / (P_b + tau):
@@ -131,12 +132,12 @@ __device__ __forceinline__ double block_sum(double* red, double x) {
   return red[0];
 }
 
-// Per-block partial sums of chi2 = sum_i w_i d_i (d_i - s_i), w = (1 - alpha)
-// / tau; optionally s_out = s (FP64, [ix][iy][iz]).  s is the iterate in
-// [ix][iy][iz] order (the z-pass state read-out).
+// Per-block partial sums of chi2 = sum_i w_i d_i (d_i - s_i), w = o / tau =
+// 1 / N (0 where unobserved); optionally s_out = s (FP64, [ix][iy][iz]).  s
+// is the iterate in [ix][iy][iz] order (the z-pass state read-out).
 template <typename R, int N>
 __global__ void __launch_bounds__(kWienerThreads)
-wiener_chi2_kernel(const R* wcoef, const double* d, const R* s, double tau, double* partial,
+wiener_chi2_kernel(const R* omw, const double* d, const R* s, double tau, double* partial,
                    double* s_out, size_t entries) {
   __shared__ double red[kWienerThreads];
   const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
@@ -144,8 +145,8 @@ wiener_chi2_kernel(const R* wcoef, const double* d, const R* s, double tau, doub
   if (idx < entries) {
     size_t va = 0, vb = 0;
     entry_voxels<R, N>(idx, va, vb);
-    const double wa = (1.0 - static_cast<double>(wcoef[idx * 4])) / tau;
-    const double wb = (1.0 - static_cast<double>(wcoef[idx * 4 + 1])) / tau;
+    const double wa = static_cast<double>(omw[idx * 2]) / tau;
+    const double wb = static_cast<double>(omw[idx * 2 + 1]) / tau;
     const double sa = s[va], sb = s[vb];
     if (wa > 0.0) x += wa * d[va] * (d[va] - sa);
     if (wb > 0.0) x += wb * d[vb] * (d[vb] - sb);
@@ -168,32 +169,32 @@ sum_partials_kernel(const double* partial, int n, double* out) {
   if (threadIdx.x == 0) out[0] = t;
 }
 
-// d chi2 / d d_i = w_i (2 d_i - s_K,i) + (1 - alpha_i) sum_k r_k,i, where r_k
-// is the adjoint field; zero on unobserved voxels.  The direct term is
+// d chi2 / d d_i = w_i (2 d_i - s_K,i) + o_i sum_k r_k,i (o = 1 - alpha), where
+// r_k is the adjoint field; zero on unobserved voxels.  The direct term is
 // written once s_K is known, the adjoint sum (acc, z-pass order) added last.
 template <typename R, int N>
 __global__ void __launch_bounds__(kWienerThreads)
-wiener_grad_direct_kernel(const R* wcoef, const double* d, const R* s, double tau, double* grad_d,
+wiener_grad_direct_kernel(const R* omw, const double* d, const R* s, double tau, double* grad_d,
                           size_t entries) {
   const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
   if (idx >= entries) return;
   size_t va = 0, vb = 0;
   entry_voxels<R, N>(idx, va, vb);
-  const double oa = 1.0 - static_cast<double>(wcoef[idx * 4]);
-  const double ob = 1.0 - static_cast<double>(wcoef[idx * 4 + 1]);
+  const double oa = static_cast<double>(omw[idx * 2]);
+  const double ob = static_cast<double>(omw[idx * 2 + 1]);
   grad_d[va] = oa / tau * (2.0 * d[va] - s[va]);
   grad_d[vb] = ob / tau * (2.0 * d[vb] - s[vb]);
 }
 
 template <typename R, int N>
 __global__ void __launch_bounds__(kWienerThreads)
-wiener_grad_adjoint_kernel(const R* wcoef, const R* acc, double* grad_d, size_t entries) {
+wiener_grad_adjoint_kernel(const R* omw, const R* acc, double* grad_d, size_t entries) {
   const size_t idx = static_cast<size_t>(blockIdx.x) * kWienerThreads + threadIdx.x;
   if (idx >= entries) return;
   size_t va = 0, vb = 0;
   entry_voxels<R, N>(idx, va, vb);
-  grad_d[va] += (1.0 - static_cast<double>(wcoef[idx * 4])) * static_cast<double>(acc[idx * 2]);
-  grad_d[vb] += (1.0 - static_cast<double>(wcoef[idx * 4 + 1])) * static_cast<double>(acc[idx * 2 + 1]);
+  grad_d[va] += static_cast<double>(omw[idx * 2]) * static_cast<double>(acc[idx * 2]);
+  grad_d[vb] += static_cast<double>(omw[idx * 2 + 1]) * static_cast<double>(acc[idx * 2 + 1]);
 }
 
 // d chi2 / d P_b (physical units) = d chi2 / d f_b * tau / (P_b + tau)^2 / V_cell.
