@@ -540,6 +540,8 @@ def main():
     ap.add_argument("--workload", default="gibbs-256^3-fp32-survey")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default path and tiles (for profiler runs)")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip timing the same problem's FP64 sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -582,7 +584,11 @@ def main():
     smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
                           seed=w.rng_seed, precision=w.precision)
     stream = torch.cuda.current_stream()
-    tune = smp.autotune(trials=30)      # set-up: picks the path and tiles, chain unchanged
+    # set-up: picks the path and tiles, chain unchanged (profiling runs keep the
+    # defaults to stay short)
+    tune = smp.autotune(trials=30) if not args.no_autotune else dict(
+        smp.tuning(), ms={"split": float("nan"), "whole": float("nan")},
+        ms_x_tile=[float("nan")] * 3, ms_y_group=[float("nan")] * 3)
     # set-up: the chain's burn-in, which also takes the GPU from its idle clock
     # (about 180 MHz) to its steady one before anything is timed
     smp.sweep(args.burn_in)
