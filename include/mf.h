@@ -309,8 +309,10 @@ mf_status mf_debug_spectrum(mf_problem* p, int32_t chain, double* buf, int32_t t
  * must outlive the graph and must not be swept on another stream while a
  * replay is in flight.  A graph replays the diagnostic recording set when it
  * was created (mf_set_diagnostics), buffers included, so that call is refused
- * for a problem while a graph over it exists.  The graph owns its side
- * streams and events.
+ * for a problem while a graph over it exists.  It also keeps the x path and
+ * tile variants chosen when it was created: a later mf_set_tuning or
+ * mf_autotune changes eager sweeps only (every choice gives the same chain
+ * up to rounding).  The graph owns its side streams and events.
  * Errors: MF_E_INVALID_ARG, MF_E_DEVICE. */
 typedef struct mf_graph mf_graph;
 mf_status mf_graph_create(mf_problem* const* problems, int32_t n, void* stream, mf_graph** out);

@@ -147,6 +147,29 @@ def test_autotune_keeps_the_chain_and_picks_a_path():
     assert np.array_equal(smp.state()[0], ref2.state()[0])
 
 
+def test_graph_keeps_the_tiles_it_captured():
+    """A graph replays the path and tile variants chosen when it was created:
+    retuning the problem afterwards changes its eager sweeps only."""
+    w = workloads.small_workload(64, 8, precision="fp32", seed=97, rng_seed=98)
+    pb = workloads.make_problem(w)
+    smp, ref = gpu_sampler(w, pb), gpu_sampler(w, pb)
+    smp.set_tuning("split", 2, 1)
+    ref.set_tuning("split", 2, 1)
+    g = binding.SweepGraph([smp])
+    smp.set_tuning("whole", 0, 0)
+    g.launch(3)
+    ref.sweep(3)
+    assert np.array_equal(smp.state()[0], ref.state()[0])
+    assert np.array_equal(smp.state()[1], ref.state()[1])
+    smp.sweep(2)                       # eager sweeps take the new choice
+    ref.set_tuning("whole", 0, 0)
+    ref.sweep(2)
+    assert np.array_equal(smp.state()[0], ref.state()[0])
+    g.close()
+    smp.close()
+    ref.close()
+
+
 def test_path_errors_and_small_grids():
     w = workloads.small_workload(16, 4, precision="fp32")
     pb = workloads.make_problem(w)
