@@ -869,9 +869,19 @@ mf_status timed_sweeps(mf_problem* p, int32_t n_sweeps, hipStream_t hs, double* 
   const mf_status room = check_sweep_room(p, n_sweeps);
   if (room != MF_OK) return room;
   const size_t half16 = evict_bytes / 32;   // 16-byte vectors per half
-  std::vector<hipEvent_t> ev(static_cast<size_t>(n_sweeps) * 2);
-  for (auto& e : ev) MF_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  // every event created is destroyed on every way out
+  std::vector<hipEvent_t> ev;
+  ev.reserve(static_cast<size_t>(n_sweeps) * 2);
   mf_status st = MF_OK;
+  auto device_ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == MF_OK) st = fail(MF_E_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
+    return st == MF_OK;
+  };
+  for (int i = 0; i < 2 * n_sweeps && st == MF_OK; ++i) {
+    hipEvent_t e = nullptr;
+    if (device_ok(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreateWithFlags"))
+      ev.push_back(e);
+  }
   for (int i = 0; i < n_sweeps && st == MF_OK; ++i) {
     const int timed = i % MF_NUM_KERNELS;
     for (int k = 0; k < MF_NUM_KERNELS && st == MF_OK; ++k) {
@@ -883,25 +893,26 @@ mf_status timed_sweeps(mf_problem* p, int32_t n_sweeps, hipStream_t hs, double* 
         if (evict_mode != 0)   // one sum per workgroup lands in the buffer's first 16 KiB
           hipLaunchKernelGGL(mf::stream_read_kernel<false>, dim3(4096), dim3(mf::kStreamThreads),
                              0, hs, src + 1024, static_cast<uint32_t*>(evict), 2 * half16 - 1024);
+        if (!device_ok(hipGetLastError(), "eviction stream launch")) break;
       }
-      if (k == timed) MF_HIP(hipEventRecord(ev[2 * i], hs));
+      if (k == timed && !device_ok(hipEventRecord(ev[2 * i], hs), "hipEventRecord")) break;
       st = launch_checked(p, kSweepOrder[k], 0, hs);
-      if (st == MF_OK && k == timed) MF_HIP(hipEventRecord(ev[2 * i + 1], hs));
+      if (st == MF_OK && k == timed) device_ok(hipEventRecord(ev[2 * i + 1], hs), "hipEventRecord");
     }
-    ++p->sweep;
+    if (st == MF_OK) ++p->sweep;
   }
-  if (st == MF_OK) {
-    MF_HIP(hipStreamSynchronize(hs));
+  if (st == MF_OK && device_ok(hipStreamSynchronize(hs), "hipStreamSynchronize")) {
     double sum[MF_NUM_KERNELS] = {0};
     int cnt[MF_NUM_KERNELS] = {0};
-    for (int i = 0; i < n_sweeps; ++i) {
+    for (int i = 0; i < n_sweeps && st == MF_OK; ++i) {
       float ms = 0.f;
-      MF_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      if (!device_ok(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "hipEventElapsedTime")) break;
       sum[i % MF_NUM_KERNELS] += ms;
       ++cnt[i % MF_NUM_KERNELS];
     }
-    for (int k = 0; k < std::min<int>(n_kernels, MF_NUM_KERNELS); ++k)
-      kernel_ms[k] = cnt[k] ? sum[k] / cnt[k] : std::numeric_limits<double>::quiet_NaN();
+    if (st == MF_OK)
+      for (int k = 0; k < std::min<int>(n_kernels, MF_NUM_KERNELS); ++k)
+        kernel_ms[k] = cnt[k] ? sum[k] / cnt[k] : std::numeric_limits<double>::quiet_NaN();
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return st;
@@ -1142,12 +1153,15 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
   for (int c = 0; c < p->desc.n_chains && st == MF_OK; ++c)
     st = mf_save_checkpoint(p, c, saved[c].data(), cb, stream);
   if (st != MF_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MF_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MF_E_DEVICE, "hipEventCreate failed");
+  }
   const DiagRec diag = p->diag;
   const int path0 = p->xpath, xv0 = p->xvar, yv0 = p->yvar;
   p->diag = DiagRec{};
-  hipEvent_t e0, e1;
-  MF_HIP(hipEventCreate(&e0));
-  MF_HIP(hipEventCreate(&e1));
   // candidates of a stage: (path, x tile, y group, slot); fastest round kept
   struct Cand { int path, xv, yv, slot; };
   auto run_stage = [&](const std::vector<Cand>& cands) {
