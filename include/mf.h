@@ -225,8 +225,9 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
  *  - x_tile: the x-pass workgroup (variant 0 is the library's tile rule,
  *    e.g. 128 iy columns x 2 k1 values at 256, with 8 LDS shell histograms
  *    per wave, for at most 255 bins; 1 is the same tile with 2 histograms
- *    per wave, for any bin count; 2 is another tile shape fixed per grid
- *    side, e.g. 64 x 4 at 256, with 2 histograms);
+ *    per wave, for any bin count; 2 splits every column over two
+ *    neighbouring lanes, 8 of its 16 rows each, e.g. 128 columns x 1 k1
+ *    value at 256, with 8 histograms per wave, for at most 255 bins);
  *  - y_group: (kz, q) units per y-pass workgroup, the rule's G, G/2, G/4
  *    (at least 1).
  * Every choice gives the same chain up to rounding (the shell sums are

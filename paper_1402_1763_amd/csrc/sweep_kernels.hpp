@@ -809,27 +809,39 @@ struct DrawCtx {
   uint32_t sweep;
 };
 
-// Signal draw of one register slot: v[r] holds t^ of mode (ix, iy, kz) with
-// ix = q + S r, r < RL (S RL = N).  Each mode is drawn from the signal
+// k2 of register e in a slot of RL registers whose modes are ix = q + S k2:
+// k2 = h0 + KS (e mod RL/2) + KS RL/2 (e div RL/2), with S KS RL = N.  A
+// whole column or pencil (KS = 1, h0 = 0) holds k2 = e; one lane of a lane
+// pair (KS = 2, RL = 8) holds the k2 of parity h0.  Registers e and e + RL/2
+// are modes ix and ix + N/2.
+template <int RL, int KS>
+__device__ __forceinline__ int k2_of(int e, int h0) {
+  return h0 + KS * (e % (RL / 2)) + KS * (RL / 2) * (e / (RL / 2));
+}
+
+// Signal draw of one register slot: v[e] holds t^ of mode (ix, iy, kz) with
+// ix = q + S k2_of(e).  Each mode is drawn from the signal
 // conditional
 //   s^ = f t^ + sqrt(v/2) (G_re + i G_im),  f = P/(P + tau), v = M tau f,
 // stored divided by M: s^/M = A_b t^ + B_b (G_re + i G_im), A_b = f/M,
 // B_b = sqrt(tau f / (2M)).  (G_re, G_im) of (ix, iy, kz) come from Philox
 // counter ((kz N + iy) N/2 + ix mod N/2, sweep, 1, chain): words (x0, x1)
-// for ix < N/2, (x2, x3) for ix >= N/2 -- modes r and r + RL/2 share a call.
+// for ix < N/2, (x2, x3) for ix >= N/2 -- registers r and r + RL/2 share a
+// call.
 // |s^/M|^2 (squared in R) is added to the lane's LDS histogram; the weight
 // w of the plane (1 on kz = 0, N/2, else 2) is applied per workgroup in
 // draw_epilogue.  This is the form for planes 0 < kz < N/2, where every
 // mode is drawn independently and q >= 1.
-template <typename R, int N, int RL, int S, bool MIX>
+template <typename R, int N, int RL, int S, bool MIX, int KS = 1>
 __device__ __forceinline__ void draw_slot_plain(cx<R>* v, int q, int iy, int kz,
-                                                const SweepArgs<R>& a, const DrawCtx<R>& d) {
+                                                const SweepArgs<R>& a, const DrawCtx<R>& d,
+                                                int h0 = 0) {
   constexpr int H = N / 2;
   const int my = wavenumber(iy, N);
   const int r2 = my * my + kz * kz;
 #pragma unroll
   for (int r = 0; r < RL / 2; ++r) {
-    const int ixl = q + S * r;   // < N/2; its partner ixl + N/2 is element r + RL/2
+    const int ixl = q + S * k2_of<RL, KS>(r, h0);   // < N/2; its partner ixl + N/2 is element r + RL/2
     R g[4];
     {
       const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
@@ -856,16 +868,17 @@ __device__ __forceinline__ void draw_slot_plain(cx<R>* v, int q, int iy, int kz,
 // the plane: self-conjugate modes are real with the full variance; the member
 // of a conjugate pair with the larger ix*N + iy uses its partner's normals
 // conjugated; q = 0 gives 0.
-template <typename R, int N, int RL, int S, bool MIX>
+template <typename R, int N, int RL, int S, bool MIX, int KS = 1>
 __device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
-                                               const SweepArgs<R>& a, const DrawCtx<R>& d) {
+                                               const SweepArgs<R>& a, const DrawCtx<R>& d,
+                                               int h0 = 0) {
   constexpr int H = N / 2;
   const int my = wavenumber(iy, N);
   const int r2 = my * my + kz * kz;
   const int py = (N - iy) % N;
 #pragma unroll
   for (int r = 0; r < RL / 2; ++r) {
-    const int ixl = q + S * r;
+    const int ixl = q + S * k2_of<RL, KS>(r, h0);
     R g[4];
     {
       const uint32_t w0 = static_cast<uint32_t>((kz * N + iy) * H + ixl);
@@ -898,7 +911,7 @@ __device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
   }
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
-    const int x = q + S * e;
+    const int x = q + S * k2_of<RL, KS>(e, h0);
     const int px = (N - x) % N;
     if (px * N + py >= x * N + iy) continue;
     const int mx = wavenumber(x, N);
@@ -919,11 +932,12 @@ __device__ __forceinline__ void draw_slot_herm(cx<R>* v, int q, int iy, int kz,
 
 // MIX = true also adds Re(conj(s^/M) t^) to the second histogram (the
 // mixing sweep's cross term).
-template <typename R, int N, int RL, int S, bool MIX = false>
+template <typename R, int N, int RL, int S, bool MIX = false, int KS = 1>
 __device__ __forceinline__ void draw_slot(cx<R>* v, int q, int iy, int kz,
-                                          const SweepArgs<R>& a, const DrawCtx<R>& d) {
-  if (kz == 0 || kz == N / 2) draw_slot_herm<R, N, RL, S, MIX>(v, q, iy, kz, a, d);
-  else draw_slot_plain<R, N, RL, S, MIX>(v, q, iy, kz, a, d);
+                                          const SweepArgs<R>& a, const DrawCtx<R>& d,
+                                          int h0 = 0) {
+  if (kz == 0 || kz == N / 2) draw_slot_herm<R, N, RL, S, MIX, KS>(v, q, iy, kz, a, d, h0);
+  else draw_slot_plain<R, N, RL, S, MIX, KS>(v, q, iy, kz, a, d, h0);
 }
 
 // Deterministic counterpart of draw_slot for the Wiener iteration: every mode
@@ -1045,41 +1059,83 @@ __device__ __forceinline__ void draw_epilogue(const SweepArgs<R>& a, int c, doub
 // equal, so more copies mean fewer lanes adding to one address per
 // instruction: the 256^3 x-pass takes 32.0 us against 33.6 us with 2
 // copies); 1 is the same tile with 2 copies, for any bin count and for the
-// mixing sweep and the Wiener iteration; 2 is another tile shape (xs_alt)
-// with 2 copies.  The autotuner chooses among them.
-//   (P, K1) of variant 2 per side: 256: (64, 4); 128: (64, 4); 96: (96, 2);
-//   80: (80, 1); 64: (64, 2); 48: (48, 1); 32: (32, 1).
-__host__ __device__ constexpr int xs_alt(int n, bool k1) {
-  switch (n) {
-    case 256: return k1 ? 4 : 64;
-    case 128: return k1 ? 4 : 64;
-    case 96: return k1 ? 2 : 96;
-    case 80: return k1 ? 1 : 80;
-    case 64: return k1 ? 2 : 64;
-    case 48: return k1 ? 1 : 48;
-    default: return k1 ? 1 : n;
-  }
-}
-
+// mixing sweep and the Wiener iteration; 2 splits every column over a pair
+// of neighbouring lanes (LANES = 2), each holding 8 of its 16 rows, with 8
+// copies: twice the waves, each with half the work, for a grid that
+// otherwise gives each SIMD few rounds of waves (below).  The autotuner
+// chooses among them.
 template <typename R, int N, int V = 0>
 struct XSTile {
   static constexpr int NA = N >= 32 ? N / 16 : 2;   // only meaningful when split_x<N>()
   static constexpr bool WIDE = N % 64 == 0 && NA >= 4 && NA % 4 == 0;
+  static constexpr int LANES = V == 2 ? 2 : 1;       // lanes per column
   static constexpr int P0 = WIDE ? (N < 128 ? N : 128) : divisor_below(N, 256 / NA);
-  static constexpr int P = V < 2 ? P0 : xs_alt(N, false);          // columns per workgroup
-  static constexpr int K1 = V < 2 ? (WIDE ? 256 / P0 : NA) : xs_alt(N, true);   // k1 values
+  static constexpr int P = V < 2 ? P0 : (N < 128 ? N : 128);       // columns per workgroup
+  static constexpr int K1 = V < 2 ? (WIDE ? 256 / P0 : NA) : divisor_below(NA, 128 / P);   // k1 values
   static constexpr int KB = NA / K1;                 // workgroups per column block
-  static constexpr int NT = P * K1;
+  static constexpr int NT = LANES * P * K1;
   static constexpr int WPP = (N / P) * KB;           // workgroups per kz plane
   static constexpr int NWAVES = (NT + 63) / 64;
-  static constexpr int HG = V == 0 ? 8 : 2;          // LDS histogram copies per wave
+  static constexpr int HG = V == 1 ? 2 : 8;          // LDS histogram copies per wave
   static constexpr int NHIST = NWAVES * HG;
-  static constexpr int MAX_BINS = V == 0 ? 255 : 1024;   // 8 copies: 64 KiB of LDS at most
-  static_assert(N % P == 0 && NA % K1 == 0 && NT <= 1024, "x-pass tile must cover the plane");
+  static constexpr int MAX_BINS = HG == 8 ? 255 : 1024;   // 8 copies: 64 KiB of LDS at most
+  static_assert(N % P == 0 && NA % K1 == 0 && NT <= 256, "x-pass tile must cover the plane");
   // FP32 at N = 256 would take 98 VGPRs (4 waves per SIMD); held to 96 (5
   // waves, no spill) the pass runs 33.2 us instead of 35.5 us.
   static constexpr int MIN_WAVES = (V < 2 && sizeof(R) == 4 && N == 256) ? 5 : 1;
 };
+
+// The value of the other lane of this lane's pair (lanes 2p and 2p + 1), by
+// a quad permutation [1, 0, 3, 2] of the wave's lanes (DPP, no LDS).
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned int>(lo)));
+}
+template <typename R>
+__device__ __forceinline__ cx<R> pair_swap(cx<R> z) {
+  return cx<R>{pair_swap(z.x), pair_swap(z.y)};
+}
+
+// x stage B of a column split over a lane pair: lane h (0 or 1) holds rows
+// 8 h + i (i < 8) of the column, x_n = Y[n][k1].  The 16-point transform's
+// first radix-2 stage (decimation in frequency) pairs rows i and i + 8: lane
+// 0 keeps x_i + x_{i+8}, lane 1 keeps (x_i - x_{i+8}) W_16^i.  The rest is an
+// 8-point transform of each lane's own values, after which register j of lane
+// h holds X[2 j + h], i.e. k2 = 2 j + h.  The same operations as the
+// 16-point transform of one lane, in the same order.
+template <typename R>
+__device__ __forceinline__ void pair_dft16_fwd(cx<R>* v, int h) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const cx<R> o = pair_swap(v[i]);
+    const cx<R> sum{v[i].x + o.x, v[i].y + o.y};
+    const cx<R> dif = rot16<R, false>(cx<R>{o.x - v[i].x, o.y - v[i].y}, i);
+    v[i] = h ? dif : sum;
+  }
+  dft<R, 8, false>(v);
+}
+
+// Its inverse, unnormalised (16 x_n, as the 16-point inverse gives): each
+// lane's 8-point inverse gives 8 (x_i + x_{i+8}) on lane 0 and
+// 8 (x_i - x_{i+8}) W_16^i on lane 1; lane 1 removes the twiddle, and the
+// pair's sum and difference give lane 0 its rows 16 x_i and lane 1 its rows
+// 16 x_{i+8}.
+template <typename R>
+__device__ __forceinline__ void pair_dft16_inv(cx<R>* v, int h) {
+  dft<R, 8, true>(v);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const cx<R> own = h ? rot16<R, true>(v[i], i) : v[i];
+    const cx<R> o = pair_swap(own);
+    v[i] = h ? cx<R>{o.x - own.x, o.y - own.y} : cx<R>{own.x + o.x, own.y + o.y};
+  }
+}
 
 template <typename R, int N, int XM, int V = 0>
 __global__ void __launch_bounds__((XSTile<R, N, V>::NT), (XSTile<R, N, V>::MIN_WAVES))
@@ -1093,6 +1149,26 @@ xsplit_kernel(SweepArgs<R> a) {
   const int c = blockIdx.z;
   constexpr int NH = XM == kXMix ? 2 : 1;
   const DrawCtx<R> d = draw_prologue<R, NT, T::NHIST, T::HG, NH>(a, c, dyn, N);
+  if constexpr (T::LANES == 2) {
+    static_assert(XM == kXSample, "the lane-pair tile serves Gibbs sweeps only");
+    // lanes 2 p and 2 p + 1 share column p: lane h holds rows 8 h .. 8 h + 7
+    const int pr = tid >> 1, h = tid & 1;
+    const int col = pr % P, k1 = (blockIdx.x % T::KB) * T::K1 + pr / P;
+    cx<R>* base = a.spec + static_cast<size_t>(c) * a.spec_stride +
+                  (static_cast<size_t>(kz) * N + 16 * k1 + 8 * h) * N + iy0 + col;
+    cx<R> v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = base[static_cast<size_t>(j) * N];
+    pair_dft16_fwd(v, h);                // v[j] = X[k1 + NA (2 j + h)]
+    __syncthreads();                     // tables and histograms ready
+    draw_slot<R, N, 8, NA, false, 2>(v, k1, iy0 + col, kz, a, d, h);
+    pair_dft16_inv(v, h);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) base[static_cast<size_t>(j) * N] = v[j];
+    const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+    draw_epilogue<R, NT, T::NHIST>(a, c, dyn, wg, (kz == 0 || kz == N / 2) ? 1.0 : 2.0);
+    return;
+  }
   const int col = tid % P, k1 = (blockIdx.x % T::KB) * T::K1 + tid / P;
   cx<R>* base = a.spec + static_cast<size_t>(c) * a.spec_stride +
                 (static_cast<size_t>(kz) * N + 16 * k1) * N + iy0 + col;

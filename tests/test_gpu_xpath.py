@@ -90,16 +90,18 @@ def test_tuning_errors():
         assert e.value.status == binding.MF_E_INVALID_ARG
     assert smp.tuning()["x_tile"] == 0 and smp.tuning()["y_group"] == 0   # the defaults
     smp.close()
-    # 8 histograms per wave (x tile 0) hold at most 255 bins
+    # 8 histograms per wave (x tiles 0 and 2) hold at most 255 bins
     w = workloads.small_workload(32, 300, precision="fp32", seed=99, rng_seed=100)
     pb = workloads.make_problem(w)
     smp = gpu_sampler(w, pb)
     assert smp.tuning()["x_tile"] == 1          # the default above 255 bins
-    with pytest.raises(binding.MFError) as e:
-        smp.set_tuning("split", 0, 0)
-    assert e.value.status == binding.MF_E_INVALID_ARG
+    for x_tile in (0, 2):
+        with pytest.raises(binding.MFError) as e:
+            smp.set_tuning("split", x_tile, 0)
+        assert e.value.status == binding.MF_E_INVALID_ARG
     res = smp.autotune(trials=1)
-    assert np.isnan(res["ms_x_tile"][0]) and res["x_tile"] != 0
+    assert np.isnan(res["ms_x_tile"][0]) and np.isnan(res["ms_x_tile"][2])
+    assert res["path"] == "whole" or res["x_tile"] == 1
     smp.close()
 
 
