@@ -142,11 +142,12 @@ def bench_batched(args):
     tuned = {}
     for (n, _), smp in zip(workloads.BATCHED_SIZES, samplers):
         res = smp.autotune(trials=10)                         # before the graph is captured
-        tuned[f"{n}^3"] = {k: res[k] for k in ("path", "x_tile", "y_group", "x_cols", "x_k1",
-                                                "x_hist", "y_units")}
+        tuned[f"{n}^3"] = {k: res[k] for k in ("path", "x_tile", "y_group", "y_radix",
+                                                "x_cols", "x_k1", "x_hist", "y_units")}
         tuned[f"{n}^3"]["ms"] = {"path": {k: _r5(v) for k, v in res["ms"].items()},
                                  "x_tile": [_r5(v) for v in res["ms_x_tile"]],
-                                 "y_group": [_r5(v) for v in res["ms_y_group"]]}
+                                 "y_group": [_r5(v) for v in res["ms_y_group"]],
+                                 "y_radix": [_r5(v) for v in res["ms_y_radix"]]}
     ms = graph_ms(max(args.warmup, 1000))
     start.record(stream)
     for _ in range(args.steps):
@@ -589,7 +590,8 @@ def main():
     # defaults to stay short)
     tune = smp.autotune(trials=30) if not args.no_autotune else dict(
         smp.tuning(), ms={"split": float("nan"), "whole": float("nan")},
-        ms_x_tile=[float("nan")] * 3, ms_y_group=[float("nan")] * 3)
+        ms_x_tile=[float("nan")] * 3, ms_y_group=[float("nan")] * 3,
+        ms_y_radix=[float("nan")] * 2)
     # set-up: the chain's burn-in, which also takes the GPU from its idle clock
     # (about 180 MHz) to its steady one before anything is timed
     smp.sweep(args.burn_in)
@@ -688,11 +690,12 @@ def main():
                    "mask": "sphere r<0.45L minus seeded 30deg wedge",
                    "chains": 1,
                    "x_path": tune["path"],
-                   "tuning": {k: tune[k] for k in ("x_tile", "y_group", "x_cols", "x_k1",
-                                                   "x_hist", "y_units")},
+                   "tuning": {k: tune[k] for k in ("x_tile", "y_group", "y_radix", "x_cols",
+                                                   "x_k1", "x_hist", "y_units")},
                    "autotune_ms_per_sweep": {k: _r5(v) for k, v in tune["ms"].items()},
                    "autotune_ms_x_tile": [_r5(v) for v in tune["ms_x_tile"]],
                    "autotune_ms_y_group": [_r5(v) for v in tune["ms_y_group"]],
+                   "autotune_ms_y_radix": [_r5(v) for v in tune["ms_y_radix"]],
                    "sweep_bytes_algorithmic": sweep_bytes,
                    "sweep_hbm_frac": round(sweep_bytes / (ms_per_step * 1e-3) / 1e9
                                            / HBM_PEAK_GBS, 4),

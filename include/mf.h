@@ -221,7 +221,7 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
  * of the x-DFT, and the x-pass runs 16-point DFTs in registers.
  * Path 1 (whole): the x-pass runs whole x pencils through LDS.  It is the
  * only path for N = 8, 16, 512.
- * On the split path two tile choices are open, three variants each:
+ * On the split path three choices are open:
  *  - x_tile: the x-pass workgroup (variant 0 is the library's tile rule,
  *    e.g. 128 iy columns x 2 k1 values at 256, with 8 LDS shell histograms
  *    per wave, for at most 255 bins; 1 is the same tile with 2 histograms
@@ -229,27 +229,33 @@ mf_status mf_mixing_sweep(mf_problem* p, int32_t n_sweeps, void* stream);
  *    neighbouring lanes, 8 of its 16 rows each, e.g. 128 columns x 1 k1
  *    value at 256, with 8 histograms per wave, for at most 255 bins);
  *  - y_group: (kz, q) units per y-pass workgroup, the rule's G, G/2, G/4
- *    (at least 1).
+ *    (at least 1);
+ *  - y_radix: the order of the y transform's radix stages, 0 the library's
+ *    schedule (e.g. 6 x 4 x 4 at 96), 1 its reverse (4 x 4 x 6).
  * Every choice gives the same chain up to rounding (the shell sums are
- * grouped by workgroup) and leaves the same state between sweeps, so choices
- * may change at any time.  The default is the split path where it exists,
- * x tile 0 (1 above 255 bins) and y group 0.  Mixing sweeps and the Wiener
- * filter always use the split path with x tile 1.
+ * grouped by workgroup, the transforms factor differently) and leaves the
+ * same state between sweeps, so choices may change at any time.  The
+ * default is the split path where it exists, x tile 0 (1 above 255 bins),
+ * y group 0 and y_radix 0.  Mixing sweeps and the Wiener filter always use
+ * the split path with x tile 1.
  * mf_set_x_path: MF_E_UNSUPPORTED_SIZE for the split path outside 32..256.
- * mf_set_tuning / mf_get_tuning: the path and both variants at once;
+ * mf_set_tuning / mf_get_tuning: the path and the three choices at once;
  *   mf_get_tuning also fills the geometry they stand for.  MF_E_INVALID_ARG
- *   for a variant outside 0..2 or an x tile whose histograms cannot hold the
- *   problem's bins, MF_E_UNSUPPORTED_SIZE as mf_set_x_path.
+ *   for a variant outside 0..2, a y_radix other than 0 or 1, or an x tile
+ *   whose histograms cannot hold the problem's bins, MF_E_UNSUPPORTED_SIZE
+ *   as mf_set_x_path.
  * mf_autotune: coordinate search over the split path's x tiles (y group 0),
- * then its y groups (with the best x tile), then that tuned split path
- * against the whole-pencil path.  Each stage times its candidates in turn,
+ * then its y groups (with the best x tile), then the y radix order where
+ * the schedule differs from its reverse, then that tuned split path against
+ * the whole-pencil path.  Each stage times its candidates in turn,
  * three rounds of `trials` Gibbs sweeps each (after one warm-up sweep, and a
  * warm-up of the device first), and keeps every candidate's fastest round;
  * an alternative replaces the first candidate of its stage (the incumbent)
  * only if faster by more than 1%.  ms (host, MF_TUNE_SLOTS doubles) receives
  * the mean sweep time in ms of every candidate: [0] the tuned split path,
- * [1] whole, [2 + v] x tile v, [5 + v] y group v, NaN for a candidate not
- * available or equal to another.  picked (may be NULL)
+ * [1] whole, [2 + v] x tile v, [5 + v] y group v, [8 + r] y radix order r,
+ * NaN for a candidate not available or equal to another.  picked (may be
+ * NULL)
  * receives the choice as mf_get_tuning gives it.  Every chain's state
  * (spectrum, P, sweep index) is saved to host memory first and restored
  * bitwise afterwards.  Diagnostic recording is suspended meanwhile.
@@ -262,8 +268,9 @@ typedef struct {
   int32_t x_k1;     /* out: k1 values per split x-pass workgroup */
   int32_t y_units;  /* out: (kz, q) units per split y-pass workgroup */
   int32_t x_hist;   /* out: LDS shell histograms per wave of the split x-pass */
+  int32_t y_radix;  /* split y-pass radix stages: 0 schedule order, 1 reversed */
 } mf_tuning;
-#define MF_TUNE_SLOTS 8
+#define MF_TUNE_SLOTS 10
 mf_status mf_set_x_path(mf_problem* p, int32_t path);
 mf_status mf_get_x_path(const mf_problem* p, int32_t* path);
 mf_status mf_set_tuning(mf_problem* p, const mf_tuning* t);

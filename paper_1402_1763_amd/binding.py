@@ -61,10 +61,11 @@ class mf_tuning(ctypes.Structure):
         ("x_k1", ctypes.c_int32),
         ("y_units", ctypes.c_int32),
         ("x_hist", ctypes.c_int32),
+        ("y_radix", ctypes.c_int32),
     ]
 
 
-MF_TUNE_SLOTS = 8
+MF_TUNE_SLOTS = 10
 
 SIGNATURES = {
     "mf_supported_n": (ctypes.c_int32, [ctypes.c_int32]),
@@ -449,17 +450,21 @@ class Sampler:
         t = mf_tuning()
         _check(load().mf_get_tuning(ctypes.c_void_p(self.handle), ctypes.byref(t)))
         return {"path": self.X_PATHS[t.x_path], "x_tile": t.x_tile, "y_group": t.y_group,
-                "x_cols": t.x_cols, "x_k1": t.x_k1, "y_units": t.y_units, "x_hist": t.x_hist}
+                "y_radix": t.y_radix, "x_cols": t.x_cols, "x_k1": t.x_k1,
+                "y_units": t.y_units, "x_hist": t.x_hist}
 
-    def set_tuning(self, path: str = "split", x_tile: int = 0, y_group: int = 0):
-        t = mf_tuning(x_path=self.X_PATHS.index(path), x_tile=x_tile, y_group=y_group)
+    def set_tuning(self, path: str = "split", x_tile: int = 0, y_group: int = 0,
+                   y_radix: int = 0):
+        t = mf_tuning(x_path=self.X_PATHS.index(path), x_tile=x_tile, y_group=y_group,
+                      y_radix=y_radix)
         _check(load().mf_set_tuning(ctypes.c_void_p(self.handle), ctypes.byref(t)))
 
     def autotune(self, trials: int = 20) -> dict:
         """Search the x path and the split path's tile variants and keep the
         fastest; returns the pick (as tuning()) with the timings:
-        "ms" {"split", "whole"}, "ms_x_tile" [3], "ms_y_group" [3] (NaN where
-        a candidate is not available or equals another).  State unchanged."""
+        "ms" {"split", "whole"}, "ms_x_tile" [3], "ms_y_group" [3],
+        "ms_y_radix" [2] (NaN where a candidate is not available or equals
+        another).  State unchanged."""
         ms = (ctypes.c_double * MF_TUNE_SLOTS)()
         t = mf_tuning()
         _check(load().mf_autotune(ctypes.c_void_p(self.handle), trials,
@@ -468,6 +473,7 @@ class Sampler:
         out["ms"] = {"split": ms[0], "whole": ms[1]}
         out["ms_x_tile"] = [ms[2], ms[3], ms[4]]
         out["ms_y_group"] = [ms[5], ms[6], ms[7]]
+        out["ms_y_radix"] = [ms[8], ms[9]]
         return out
 
     def sweep_bytes(self) -> dict:

@@ -75,6 +75,13 @@ struct Geometry {
     if constexpr (mf::split_x<N>()) return mf::YSTile<R, N, V>::G;
     else return 0;
   }
+  // the y transform's radix schedule differs from its reverse (it is not a
+  // palindrome, e.g. 6 x 4 x 4 at 96 but 16 x 16 at 256)
+  static constexpr bool y_rev_distinct() {
+    for (int i = 0; i < mf::Radices<N>::n; ++i)
+      if (mf::Radices<N>::r[i] != mf::Radices<N>::r[mf::Radices<N>::n - 1 - i]) return true;
+    return false;
+  }
   template <int V>
   static constexpr int x_cols() {
     if constexpr (mf::split_x<N>()) return mf::XSTile<R, N, V>::P;
@@ -107,6 +114,7 @@ struct Shape {
   int x_hist[kTileVariants];     // LDS histogram copies per wave
   int x_max_bins[kTileVariants]; // most bins whose histograms fit the variant's LDS
   int y_units[kTileVariants];    // (kz, q) units per split y-pass workgroup, per variant
+  int y_rev_distinct;            // the y radix schedule differs from its reverse
   int xp_whole;                  // whole-pencil x-pass workgroups per kz plane
   int ztiles;                    // z-pass tiles per chain
   int zept;                      // elements per z-pass lane (observation bits per tile)
@@ -125,7 +133,7 @@ Shape shape_of(int n) {
                  {G::template x_max_bins<0>(), G::template x_max_bins<1>(),                   \
                   G::template x_max_bins<2>()},                                            \
                  {G::template y_units<0>(), G::template y_units<1>(), G::template y_units<2>()}, \
-                 G::xp_whole, G::ztiles, G::zept};                                         \
+                 G::y_rev_distinct() ? 1 : 0, G::xp_whole, G::ztiles, G::zept};           \
   }
     MF_SHAPE(8) MF_SHAPE(16) MF_SHAPE(32) MF_SHAPE(48) MF_SHAPE(64) MF_SHAPE(80) MF_SHAPE(96)
     MF_SHAPE(128) MF_SHAPE(256) MF_SHAPE(512)
@@ -282,6 +290,7 @@ struct mf_problem {
   std::vector<int> obs_chunks;  // per chain: z-pass (tile, element) chunks holding an observed voxel
   int xpath;                    // XPath of Gibbs sweeps
   int xvar = 0, yvar = 0;       // split-path tile variants of Gibbs sweeps (autotuner)
+  int yrad = 0;                 // 1: the split y-passes run their radix stages reversed
   int graphs = 0;               // live graphs that captured this problem's sweep
   // x-pass workgroups of a path; the split path's with x-tile variant xv
   int n_wg(int path, int xv) const { return path == kPathSplit ? L.n_wg_split[xv] : L.n_wg_whole; }
@@ -345,13 +354,27 @@ enum KernelId {
   kZDetK = 13, kZAccK = 14, kXDetK = 15, kXAdjK = 16, kXMixK = 17, kMixPkK = 18, kXMixInvK = 19
 };
 
-// Split-path y-pass with units variant V.
-template <typename R, int N, bool INV, int V>
+// Split-path y-pass with units variant V and radix order RV.
+template <typename R, int N, bool INV, int V, bool RV>
 void launch_ysplit(const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
   using YS = mf::YSTile<R, N, V>;
   const int extra = INV ? a.nb : 0;   // the P(k) workgroups
-  hipLaunchKernelGGL((mf::ysplit_kernel<R, N, INV, V>), dim3(16 / YS::G * (N / 2 + 1) + extra, 1, nch),
-                     dim3(YS::NT), 0, st, a);
+  hipLaunchKernelGGL((mf::ysplit_kernel<R, N, INV, V, RV>),
+                     dim3(16 / YS::G * (N / 2 + 1) + extra, 1, nch), dim3(YS::NT), 0, st, a);
+}
+
+// The split y-pass of y variant yv: units variant yv % 3 (G, G/2, G/4), radix
+// stages in reversed order when yv >= 3.
+template <typename R, int N, bool INV>
+void launch_ysplit_v(const mf::SweepArgs<R>& a, int nch, hipStream_t st, int yv) {
+  switch (yv) {
+    case 1: launch_ysplit<R, N, INV, 1, false>(a, nch, st); break;
+    case 2: launch_ysplit<R, N, INV, 2, false>(a, nch, st); break;
+    case 3: launch_ysplit<R, N, INV, 0, true>(a, nch, st); break;
+    case 4: launch_ysplit<R, N, INV, 1, true>(a, nch, st); break;
+    case 5: launch_ysplit<R, N, INV, 2, true>(a, nch, st); break;
+    default: launch_ysplit<R, N, INV, 0, false>(a, nch, st); break;
+  }
 }
 
 // Split-path Gibbs x-pass with tile variant V.
@@ -363,8 +386,9 @@ void launch_xsplit(const mf::SweepArgs<R>& a, int nch, hipStream_t st) {
                      dim3(XS::NT), mf::hist_doubles(XS::NHIST, a.nb, 1) * sizeof(double) + tables, st, a);
 }
 
-// xv, yv: split-path tile variants of the Gibbs x-pass and of the y-passes;
-// the other x-pass modes (mixing, Wiener) run x-tile variant 1.
+// xv, yv: split-path tile variants of the Gibbs x-pass and of the y-passes
+// (yv: units variant + 3 x radix order, launch_ysplit_v); the other x-pass
+// modes (mixing, Wiener) run x-tile variant 1.
 template <typename R, int N>
 void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool whole, int xv,
               int yv) {
@@ -395,9 +419,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
     case kYF:
       if constexpr (can_split) {
         if (split) {
-          if (yv == 1) launch_ysplit<R, N, false, 1>(a, nch, st);
-          else if (yv == 2) launch_ysplit<R, N, false, 2>(a, nch, st);
-          else launch_ysplit<R, N, false, 0>(a, nch, st);
+          launch_ysplit_v<R, N, false>(a, nch, st, yv);
           break;
         }
       }
@@ -407,9 +429,7 @@ void launch_n(int id, const mf::SweepArgs<R>& a, int nch, hipStream_t st, bool w
     case kYI:
       if constexpr (can_split) {
         if (split) {
-          if (yv == 1) launch_ysplit<R, N, true, 1>(a, nch, st);
-          else if (yv == 2) launch_ysplit<R, N, true, 2>(a, nch, st);
-          else launch_ysplit<R, N, true, 0>(a, nch, st);
+          launch_ysplit_v<R, N, true>(a, nch, st, yv);
           break;
         }
       }
@@ -479,7 +499,7 @@ void launch(int id, const mf::SweepArgs<R>& a, int n, int nch, hipStream_t st, b
 mf_status launch_checked(mf_problem* p, int id, int staging_chain, hipStream_t st, int path = -1,
                          int pk_mode = mf::kPkDraw) {
   const int nch = p->desc.n_chains;
-  const int xv = path < 0 ? p->xvar : 1, yv = p->yvar;
+  const int xv = path < 0 ? p->xvar : 1, yv = p->yvar + 3 * p->yrad;
   if (path < 0) path = p->xpath;
   if (p->fp64()) {
     auto a = args_of<double>(p, path, xv);
@@ -1070,6 +1090,8 @@ mf_status mf_set_tuning(mf_problem* p, const mf_tuning* t) {
   if (!p || !t) return fail(MF_E_INVALID_ARG, "NULL argument");
   if (t->x_tile < 0 || t->x_tile >= kTileVariants || t->y_group < 0 || t->y_group >= kTileVariants)
     return fail(MF_E_INVALID_ARG, "tile variants must be 0..%d", kTileVariants - 1);
+  if (t->y_radix != 0 && t->y_radix != 1)
+    return fail(MF_E_INVALID_ARG, "y_radix must be 0 (schedule order) or 1 (reversed)");
   if (t->x_path == kPathSplit && p->desc.n >= 32 && p->desc.n <= 256 &&
       p->desc.n_bins > p->sh.x_max_bins[t->x_tile])
     return fail(MF_E_INVALID_ARG, "x tile %d holds histograms for at most %d bins (problem has %d)",
@@ -1078,6 +1100,7 @@ mf_status mf_set_tuning(mf_problem* p, const mf_tuning* t) {
   if (st != MF_OK) return st;
   p->xvar = t->x_tile;
   p->yvar = t->y_group;
+  p->yrad = t->y_radix;
   return MF_OK;
 }
 
@@ -1091,6 +1114,7 @@ mf_status mf_get_tuning(const mf_problem* p, mf_tuning* t) {
   t->x_k1 = split ? p->sh.x_k1[p->xvar] : 0;
   t->x_hist = split ? p->sh.x_hist[p->xvar] : 0;
   t->y_units = split ? p->sh.y_units[p->yvar] : 0;
+  t->y_radix = split ? p->yrad : 0;
   return MF_OK;
 }
 
@@ -1100,12 +1124,13 @@ namespace {
 
 // Mean ms of `trials` Gibbs sweeps (after one warm-up sweep) with the given
 // choices; restores nothing (the caller saved the chains).
-mf_status time_choice(mf_problem* p, int path, int xv, int yv, int trials, void* stream,
+mf_status time_choice(mf_problem* p, int path, int xv, int yv, int yr, int trials, void* stream,
                       hipEvent_t e0, hipEvent_t e1, double* ms) {
   hipStream_t hs = static_cast<hipStream_t>(stream);
   p->xpath = path;
   p->xvar = xv;
   p->yvar = yv;
+  p->yrad = yr;
   mf_status st = mf_gibbs_sweep(p, 1, stream);
   if (st != MF_OK) return st;
   MF_HIP(hipEventRecord(e0, hs));
@@ -1138,12 +1163,13 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
     p->xpath = kPathWhole;
     p->xvar = p->default_xvar();
     p->yvar = 0;
+    p->yrad = 0;
     return picked ? mf_get_tuning(p, picked) : MF_OK;
   }
   // every candidate's sweeps must fit below the 2^32 sweep-index bound; the
   // chains are restored afterwards
   const int warm = std::max<int>(trials, 20);
-  const int64_t budget = static_cast<int64_t>(kTuneRounds) * 8 * (trials + 1) + warm;
+  const int64_t budget = static_cast<int64_t>(kTuneRounds) * 10 * (trials + 1) + warm;
   mf_status st = check_sweep_room(p, budget);
   if (st != MF_OK) return st;
   // Save every chain (spectrum, P, sweep index) and switch recording off, so
@@ -1160,15 +1186,16 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
     return fail(MF_E_DEVICE, "hipEventCreate failed");
   }
   const DiagRec diag = p->diag;
-  const int path0 = p->xpath, xv0 = p->xvar, yv0 = p->yvar;
+  const int path0 = p->xpath, xv0 = p->xvar, yv0 = p->yvar, yr0 = p->yrad;
   p->diag = DiagRec{};
-  // candidates of a stage: (path, x tile, y group, slot); fastest round kept
-  struct Cand { int path, xv, yv, slot; };
+  // candidates of a stage: (path, x tile, y group, y radix order, slot);
+  // fastest round kept
+  struct Cand { int path, xv, yv, yr, slot; };
   auto run_stage = [&](const std::vector<Cand>& cands) {
     for (int r = 0; r < kTuneRounds && st == MF_OK; ++r)
       for (const Cand& c : cands) {
         double t = 0.0;
-        st = time_choice(p, c.path, c.xv, c.yv, trials, stream, e0, e1, &t);
+        st = time_choice(p, c.path, c.xv, c.yv, c.yr, trials, stream, e0, e1, &t);
         if (st != MF_OK) return;
         if (!(ms[c.slot] <= t)) ms[c.slot] = t;   // NaN or slower: replace
       }
@@ -1184,21 +1211,30 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
   p->xpath = kPathSplit;
   p->xvar = p->default_xvar();
   p->yvar = 0;
+  p->yrad = 0;
   st = mf_gibbs_sweep(p, warm, stream);   // device warm-up
   // 1. x tiles on the split path, y group 0
   std::vector<Cand> xs;
   for (int v = 0; v < kTileVariants; ++v)
-    if (p->desc.n_bins <= p->sh.x_max_bins[v]) xs.push_back({kPathSplit, v, 0, 2 + v});
+    if (p->desc.n_bins <= p->sh.x_max_bins[v]) xs.push_back({kPathSplit, v, 0, 0, 2 + v});
   run_stage(xs);
   const int best_x = st == MF_OK ? xs[pick(xs)].xv : 0;
   // 2. y groups with the best x tile (groups of equal size are timed once)
-  std::vector<Cand> ys{{kPathSplit, best_x, 0, 5}};
+  std::vector<Cand> ys{{kPathSplit, best_x, 0, 0, 5}};
   for (int v = 1; v < kTileVariants; ++v)
-    if (p->sh.y_units[v] != p->sh.y_units[v - 1]) ys.push_back({kPathSplit, best_x, v, 5 + v});
+    if (p->sh.y_units[v] != p->sh.y_units[v - 1]) ys.push_back({kPathSplit, best_x, v, 0, 5 + v});
   if (st == MF_OK) run_stage(ys);
   const int best_y = st == MF_OK ? ys[pick(ys)].yv : 0;
-  // 3. the split path so tuned against the whole-pencil path
-  std::vector<Cand> paths{{kPathSplit, best_x, best_y, 0}, {kPathWhole, 0, 0, 1}};
+  // 3. the y transform's radix schedule in order or reversed, where the two
+  // differ
+  int best_r = 0;
+  if (st == MF_OK && p->sh.y_rev_distinct) {
+    std::vector<Cand> rs{{kPathSplit, best_x, best_y, 0, 8}, {kPathSplit, best_x, best_y, 1, 9}};
+    run_stage(rs);
+    if (st == MF_OK) best_r = rs[pick(rs)].yr;
+  }
+  // 4. the split path so tuned against the whole-pencil path
+  std::vector<Cand> paths{{kPathSplit, best_x, best_y, best_r, 0}, {kPathWhole, 0, 0, 0, 1}};
   if (st == MF_OK) run_stage(paths);
   const bool whole = st == MF_OK && pick(paths) == 1;
   (void)hipEventDestroy(e0);
@@ -1207,6 +1243,7 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
   p->xpath = path0;
   p->xvar = xv0;
   p->yvar = yv0;
+  p->yrad = yr0;
   for (int c = 0; c < p->desc.n_chains; ++c) {
     const mf_status r = mf_load_checkpoint(p, c, saved[c].data(), cb, stream);
     if (st == MF_OK) st = r;
@@ -1215,6 +1252,7 @@ mf_status mf_autotune(mf_problem* p, int32_t trials, void* stream, double* ms, m
   p->xpath = whole ? kPathWhole : kPathSplit;
   p->xvar = whole ? p->default_xvar() : best_x;
   p->yvar = whole ? 0 : best_y;
+  p->yrad = whole ? 0 : best_r;
   return picked ? mf_get_tuning(p, picked) : MF_OK;
 }
 

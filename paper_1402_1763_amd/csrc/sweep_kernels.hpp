@@ -682,7 +682,11 @@ struct YSTile {
   using TL = Tile<N, G * NA, NT, false, PSTR, PADS>;
 };
 
-template <typename R, int N, bool INV, int V = 0>
+// RV runs the y transform's radix stages in reversed order (e.g. 4 x 4 x 6
+// instead of 6 x 4 x 4 at 96): a choice of the radix schedule that changes
+// no stored layout, since the transform's output and input pass through LDS
+// in natural order.
+template <typename R, int N, bool INV, int V = 0, bool RV = false>
 __global__ void __launch_bounds__((YSTile<R, N, V>::NT))
 ysplit_kernel(SweepArgs<R> a) {
   using T = YSTile<R, N, V>;
@@ -715,15 +719,15 @@ ysplit_kernel(SweepArgs<R> a) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       int pen = 0, n = 0;
-      TL::template in_pos<false>(tid, e, pen, n);
+      TL::template in_pos<RV>(tid, e, pen, n);
       v[e] = plane[static_cast<size_t>(row_of(pen)) * N + n];
     }
-    fft_regs<R, N, TL, NT, false, false>(v, lds, tw);
+    fft_regs<R, N, TL, NT, false, RV>(v, lds, tw);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       int pen = 0, n = 0;
-      TL::template out_pos<false>(tid, e, pen, n);
+      TL::template out_pos<RV>(tid, e, pen, n);
       lds[TL::lidx(pen, n)] = v[e];
     }
     __syncthreads();
@@ -762,15 +766,15 @@ ysplit_kernel(SweepArgs<R> a) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       int pen = 0, n = 0;
-      TL::template in_pos<false>(tid, e, pen, n);
+      TL::template in_pos<RV>(tid, e, pen, n);
       v[e] = lds[TL::lidx(pen, n)];
     }
     __syncthreads();   // the transform below rewrites the buffer
-    fft_regs<R, N, TL, NT, true, false>(v, lds, tw);
+    fft_regs<R, N, TL, NT, true, RV>(v, lds, tw);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       int pen = 0, n = 0;
-      TL::template out_pos<false>(tid, e, pen, n);
+      TL::template out_pos<RV>(tid, e, pen, n);
       plane[static_cast<size_t>(row_of(pen)) * N + n] = v[e];
     }
   }

@@ -44,16 +44,17 @@ def test_every_path_and_tile_at_256_matches_oracle():
     pb = workloads.make_problem(w)
     print("256^3: oracle 2 sweeps", flush=True)
     s_ref, p_ref = run_oracle(w, pb, 2)
-    for path, x_tile in (("whole", 0), ("split", 0), ("split", 1), ("split", 2)):
+    for path, x_tile, y_radix in (("whole", 0, 0), ("split", 0, 0), ("split", 1, 0),
+                                  ("split", 2, 0), ("split", 0, 1)):
         smp = gpu_sampler(w, pb)
-        smp.set_tuning(path, x_tile, 0)
+        smp.set_tuning(path, x_tile, 0, y_radix)
         smp.sweep(2)
         s_gpu, p_gpu, _ = smp.state()
         geo = smp.tuning()
         smp.close()
         err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
         print(f"  {path} x_tile={x_tile} ({geo['x_cols']} x {geo['x_k1']}, {geo['x_hist']} "
-              f"histograms per wave): err_s={err_s:.3e} "
+              f"histograms per wave) y_radix={y_radix}: err_s={err_s:.3e} "
               f"err_P={err_p:.3e}", flush=True)
         assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
 
@@ -80,15 +81,37 @@ def test_tile_variants_match_oracle(precision, n, x_tile, y_group):
     assert err_s < TOL[precision] and err_p < TOL[precision]
 
 
+@pytest.mark.parametrize("precision,n", [("fp64", 32), ("fp32", 48), ("fp64", 80), ("fp32", 96),
+                                         ("fp32", 128), ("fp64", 96)])
+@pytest.mark.parametrize("y_group", [0, 1])
+def test_reversed_y_radix_order_matches_oracle(precision, n, y_group):
+    """The y transform's radix stages in reversed order (e.g. 4 x 4 x 6 at
+    96), against the oracle over 3 sweeps."""
+    w = workloads.small_workload(n, 8, precision=precision, seed=89, rng_seed=90)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    smp.set_tuning("split", 0, y_group, 1)
+    assert smp.tuning()["y_radix"] == 1
+    smp.sweep(3)
+    s_gpu, p_gpu, _ = smp.state()
+    smp.close()
+    s_ref, p_ref = run_oracle(w, pb, 3)
+    err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+    print(f"n={n} {precision} y radix reversed, y_group={y_group}: err_s={err_s:.3e} "
+          f"err_P={err_p:.3e}", flush=True)
+    assert err_s < TOL[precision] and err_p < TOL[precision]
+
+
 def test_tuning_errors():
     w = workloads.small_workload(32, 4, precision="fp32", seed=99, rng_seed=100)
     pb = workloads.make_problem(w)
     smp = gpu_sampler(w, pb)
-    for bad in ((0, 3, 0), (0, 0, -1)):
+    for bad in ((3, 0, 0), (0, -1, 0), (0, 0, 2), (0, 0, -1)):
         with pytest.raises(binding.MFError) as e:
-            smp.set_tuning("split", bad[1], bad[2])
+            smp.set_tuning("split", *bad)
         assert e.value.status == binding.MF_E_INVALID_ARG
-    assert smp.tuning()["x_tile"] == 0 and smp.tuning()["y_group"] == 0   # the defaults
+    t = smp.tuning()
+    assert (t["x_tile"], t["y_group"], t["y_radix"]) == (0, 0, 0)   # the defaults
     smp.close()
     # 8 histograms per wave (x tiles 0 and 2) hold at most 255 bins
     w = workloads.small_workload(32, 300, precision="fp32", seed=99, rng_seed=100)
@@ -144,9 +167,23 @@ def test_autotune_keeps_the_chain_and_picks_a_path():
     # the default path and the last two on the chosen one
     ref2 = gpu_sampler(w, pb)
     ref2.sweep(3)
-    ref2.set_tuning(res["path"], res["x_tile"], res["y_group"])
+    ref2.set_tuning(res["path"], res["x_tile"], res["y_group"], res["y_radix"])
     ref2.sweep(2)
     assert np.array_equal(smp.state()[0], ref2.state()[0])
+    # 8 x 8 at 64 reads the same both ways: the radix order is not timed
+    assert all(np.isnan(v) for v in res["ms_y_radix"])
+
+
+def test_autotune_times_the_radix_order_where_it_differs():
+    w = workloads.small_workload(48, 8, precision="fp32", seed=87, rng_seed=88)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    res = smp.autotune(trials=2)
+    print("autotune 48^3", res, flush=True)
+    assert all(np.isfinite(v) and v > 0 for v in res["ms_y_radix"])
+    assert res["path"] == "whole" or res["y_radix"] in (0, 1)
+    assert smp.tuning() == {k: v for k, v in res.items() if not k.startswith("ms")}
+    smp.close()
 
 
 def test_graph_keeps_the_tiles_it_captured():
