@@ -15,7 +15,7 @@ event-timed sweeps (one kernel per sweep between fenceless events), once in
 sequence and once with the 256 MB last-level cache evicted before the kernel.
 
 Prints one JSON line.  --gpus N > 1 is refused: the sampler runs one chain
-per GPU and this build measures one GPU.
+per GPU, and the benchmark measures one GPU.
 """
 from __future__ import annotations
 

@@ -50,8 +50,8 @@ def build(verbose: bool = False, extra_flags=None) -> str:
 # Host half under AddressSanitizer and UndefinedBehaviorSanitizer, for the
 # CPU tests of the C ABI's host code (argument and descriptor validation,
 # set-up tables, error clean-up).  Every sanitizer flag is host-only; the
-# device code is compiled unoptimised (it is never run from this build) to
-# keep the build short.  Load it with the sanitizer runtime preloaded
+# device code is compiled unoptimised (the sanitized library never launches
+# it) to keep the compilation short.  Load it with the sanitizer runtime preloaded
 # (host_sanitizer_runtime()) and MFGIBBS_LIB pointing at it.
 SANITIZE_FLAGS = [
     "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-shared-libsan",
