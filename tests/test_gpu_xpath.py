@@ -187,13 +187,14 @@ def test_autotune_times_the_radix_order_where_it_differs():
 
 
 def test_graph_keeps_the_tiles_it_captured():
-    """A graph replays the path and tile variants chosen when it was created:
-    retuning the problem afterwards changes its eager sweeps only."""
-    w = workloads.small_workload(64, 8, precision="fp32", seed=97, rng_seed=98)
+    """A graph replays the path, tile variants and radix order chosen when it
+    was created: retuning the problem afterwards changes its eager sweeps
+    only."""
+    w = workloads.small_workload(48, 8, precision="fp32", seed=97, rng_seed=98)
     pb = workloads.make_problem(w)
     smp, ref = gpu_sampler(w, pb), gpu_sampler(w, pb)
-    smp.set_tuning("split", 2, 1)
-    ref.set_tuning("split", 2, 1)
+    smp.set_tuning("split", 2, 1, 1)
+    ref.set_tuning("split", 2, 1, 1)
     g = binding.SweepGraph([smp])
     smp.set_tuning("whole", 0, 0)
     g.launch(3)
