@@ -19,18 +19,25 @@ def _device():
     torch.cuda.set_device(0)
 
 
-@pytest.mark.parametrize("precision,n", [("fp64", 32), ("fp32", 64)])
-def test_chains_in_one_problem_match_oracle(precision, n):
+@pytest.mark.parametrize("precision,n,tuning", [
+    ("fp64", 32, None), ("fp32", 64, None),
+    # every chain of a multi-chain launch under the variants the autotuner
+    # may pick: the lane-pair x tile, G/2 y groups, reversed radix order
+    ("fp32", 96, ("split", 2, 1, 1)), ("fp64", 48, ("split", 2, 0, 1)),
+    ("fp32", 80, ("whole", 0, 0, 0))])
+def test_chains_in_one_problem_match_oracle(precision, n, tuning):
     ws, pbs = [], []
     for c in range(3):
         w = workloads.small_workload(n, 8, mask="random", precision=precision, seed=40 + c,
                                      rng_seed=77, mask_frac=0.1 + 0.1 * c, sigma2=0.5 + c)
         ws.append(w)
         pbs.append(workloads.make_problem(w))
-    print(f"3 chains n={n} {precision}", flush=True)
+    print(f"3 chains n={n} {precision} tuning={tuning}", flush=True)
     smp = binding.Sampler([pb["data"] for pb in pbs], [pb["noise_var"] for pb in pbs],
                           [pb["pk_init"] for pb in pbs], 8, ws[0].box, seed=77,
                           precision=precision, chain_id=5)
+    if tuning is not None:
+        smp.set_tuning(*tuning)
     smp.sweep(6)
     for c in range(3):
         s_gpu, p_gpu, done = smp.state(c)
