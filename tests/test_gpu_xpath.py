@@ -39,7 +39,9 @@ def test_whole_path_matches_oracle(precision, n):
 @pytest.mark.timeout(600)
 def test_every_path_and_tile_at_256_matches_oracle():
     """The benchmarked 256^3 survey problem, 2 sweeps, on the whole-pencil path
-    and on the split path with each x-tile variant, against the oracle."""
+    and on the split path with each x-tile variant and the reversed radix
+    order, against the oracle (FP32, and FP64 for the lane-pair tile and the
+    reversed order)."""
     w = workloads.SURVEY_256_MIXED
     pb = workloads.make_problem(w)
     print("256^3: oracle 2 sweeps", flush=True)
@@ -57,6 +59,19 @@ def test_every_path_and_tile_at_256_matches_oracle():
               f"histograms per wave) y_radix={y_radix}: err_s={err_s:.3e} "
               f"err_P={err_p:.3e}", flush=True)
         assert err_s < TOL["fp32"] and err_p < TOL["fp32"]
+    # the same chain in FP64 mode (the oracle draws the same numbers) under the
+    # lane-pair tile and the reversed radix order
+    for x_tile, y_radix in ((2, 0), (0, 1)):
+        smp = binding.Sampler(pb["data"], pb["noise_var"], pb["pk_init"], w.n_bins, w.box,
+                              seed=w.rng_seed, precision="fp64")
+        smp.set_tuning("split", x_tile, 0, y_radix)
+        smp.sweep(2)
+        s_gpu, p_gpu, _ = smp.state()
+        smp.close()
+        err_s, err_p = errors(s_gpu, p_gpu, s_ref, p_ref)
+        print(f"  fp64 split x_tile={x_tile} y_radix={y_radix}: err_s={err_s:.3e} "
+              f"err_P={err_p:.3e}", flush=True)
+        assert err_s < TOL["fp64"] and err_p < TOL["fp64"]
 
 
 @pytest.mark.parametrize("precision,n", [("fp32", 64), ("fp64", 96), ("fp32", 80), ("fp64", 128)])
