@@ -117,6 +117,33 @@ def test_reversed_y_radix_order_matches_oracle(precision, n, y_group):
     assert err_s < TOL[precision] and err_p < TOL[precision]
 
 
+@pytest.mark.parametrize("n,expect", [
+    # x tile -> (iy columns, k1 values, histograms per wave); y group -> units
+    (256, {0: (128, 2, 8), 1: (128, 2, 2), 2: (128, 1, 8), "y": (1, 1, 1)}),
+    (128, {0: (128, 2, 8), 1: (128, 2, 2), 2: (128, 1, 8), "y": (4, 2, 1)}),
+    (96, {0: (32, 6, 8), 1: (32, 6, 2), 2: (96, 1, 8), "y": (4, 2, 1)}),
+    (64, {0: (64, 4, 8), 1: (64, 4, 2), 2: (64, 2, 8), "y": (16, 8, 4)}),
+])
+def test_tuning_reports_the_documented_geometry(n, expect):
+    """mf_get_tuning's geometry of every variant: the rule tile (128 columns x
+    256/128 k1 values from 128 up), its 2-histogram twin, the lane-pair tile
+    (two lanes per column) and the y groups G, G/2, G/4."""
+    w = workloads.small_workload(n, 8, precision="fp32", seed=85, rng_seed=86)
+    pb = workloads.make_problem(w)
+    smp = gpu_sampler(w, pb)
+    for x_tile in range(3):
+        smp.set_tuning("split", x_tile, 0)
+        t = smp.tuning()
+        assert (t["x_cols"], t["x_k1"], t["x_hist"]) == expect[x_tile], (x_tile, t)
+    for y_group in range(3):
+        smp.set_tuning("split", 0, y_group)
+        assert smp.tuning()["y_units"] == expect["y"][y_group], (y_group, smp.tuning())
+    smp.set_tuning("whole", 0, 0)
+    t = smp.tuning()
+    assert (t["x_cols"], t["x_k1"], t["x_hist"], t["y_units"], t["y_radix"]) == (0, 0, 0, 0, 0)
+    smp.close()
+
+
 def test_tuning_errors():
     w = workloads.small_workload(32, 4, precision="fp32", seed=99, rng_seed=100)
     pb = workloads.make_problem(w)
